@@ -73,8 +73,10 @@ typedef struct {
 } efm_enum_opts;
 
 #define EFM_OPT_NO_PRUNE 1u      /* skip the found-set minimality prune (result unchanged) */
-#define EFM_OPT_DEBUG_PRIME 2u   /* use the tiny prime 3 for the modular rank (forces the exact
-                                    confirmation path; result unchanged) */
+#define EFM_OPT_EXACT_RANK 2u    /* decide every rank test in exact integer arithmetic instead of
+                                    modulo a prime first (slower; result unchanged) */
+#define EFM_OPT_TIME_KERNELS 4u  /* record HIP events around every kernel launch on the stream and
+                                    report per-level kernel times in efm_level_stats */
 
 /* Per-level counters (level k = partial pathways of k reactions). */
 typedef struct {
@@ -86,6 +88,11 @@ typedef struct {
   int64_t independent;  /* distinct children with independent columns */
   int64_t emitted;      /* elementary pathways found */
   int64_t kept;         /* frontier members of the next level (after the cap) */
+  double ms_expand;     /* kernel times on the stream (EFM_OPT_TIME_KERNELS only, else 0) */
+  double ms_rank;
+  double ms_exact;
+  double ms_select;
+  double ms_materialize;
 } efm_level_stats;
 
 /* Create a network from S (Section 2.1).

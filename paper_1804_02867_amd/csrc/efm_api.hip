@@ -1,0 +1,543 @@
+// efm_api.hip -- host side of the C ABI (include/efm.h): network tables, the
+// workspace layout and the level loop that drives the kernels.
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/efm.h"
+#include "efm_internal.h"
+
+using efm::u64;
+
+namespace {
+
+thread_local std::string g_err;
+
+efm_status fail(efm_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (expr);                                                               \
+    if (e_ != hipSuccess) {                                                               \
+      rc = fail(EFM_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));              \
+      goto done;                                                                          \
+    }                                                                                     \
+  } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// splitmix64, for the Zobrist keys of the child hash
+u64 splitmix64(u64 &state) {
+  u64 z = (state += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// supported (reaction words, metabolite words) instantiations
+const int kShapes[][2] = {{1, 1}, {1, 2}, {2, 1}, {2, 2}, {2, 4}, {4, 1}, {4, 2}, {4, 4},
+                          {8, 2}, {8, 4}, {8, 8}, {16, 4}, {16, 8}, {16, 16}};
+
+}  // namespace
+
+struct efm_network {
+  int m = 0, n = 0, mi = 0, W = 0, Wt = 0, MWt = 0;
+  std::vector<int32_t> S;
+  std::vector<uint8_t> rev, ext;
+  std::vector<int> int_row;   // internal metabolite -> row of S
+  void *blob = nullptr;
+  efm::DevNet dn{};
+};
+
+struct efm_result {
+  int W = 0, n = 0;
+  uint32_t status = 0;
+  int64_t count = 0;
+  std::vector<u64> keys;
+  std::vector<int64_t> flux;
+  std::vector<efm_level_stats> levels;
+};
+
+extern "C" {
+
+const char *efm_last_error(void) { return g_err.c_str(); }
+
+const char *efm_status_string(efm_status s) {
+  switch (s) {
+    case EFM_OK: return "ok";
+    case EFM_EINVAL: return "invalid argument";
+    case EFM_ENOMEM: return "workspace or capacity too small";
+    case EFM_EDEVICE: return "HIP error";
+    case EFM_EOVERFLOW: return "integer overflow";
+    default: return "unknown status";
+  }
+}
+
+efm_status efm_network_create(int32_t n_met, int32_t n_rxn, const int32_t *S, const uint8_t *reversible,
+                              const uint8_t *external, efm_network **out) {
+  if (!S || !reversible || !external || !out) return fail(EFM_EINVAL, "null pointer");
+  if (n_met <= 0 || n_rxn <= 0 || n_rxn > EFM_MAX_RXN)
+    return fail(EFM_EINVAL, "bad dimensions %d x %d (reactions must be 1..%d)", n_met, n_rxn, EFM_MAX_RXN);
+  efm_network *N = new (std::nothrow) efm_network;
+  if (!N) return fail(EFM_ENOMEM, "host allocation failed");
+  N->m = n_met;
+  N->n = n_rxn;
+  N->S.assign(S, S + (size_t)n_met * n_rxn);
+  N->rev.assign(reversible, reversible + n_rxn);
+  N->ext.assign(external, external + n_met);
+  for (int i = 0; i < n_met; ++i)
+    if (!N->ext[i]) N->int_row.push_back(i);
+  N->mi = (int)N->int_row.size();
+  N->W = (n_rxn + 63) / 64;
+  const int MW = std::max(1, (N->mi + 63) / 64);
+  if (N->mi > 1024) {
+    delete N;
+    return fail(EFM_EINVAL, "%d internal metabolites (at most 1024)", (int)N->mi);
+  }
+  for (auto &sh : kShapes)
+    if (sh[0] >= N->W && sh[1] >= MW) { N->Wt = sh[0]; N->MWt = sh[1]; break; }
+  const int n = n_rxn, mi = N->mi, Wt = N->Wt, MWt = N->MWt;
+
+  // host tables
+  std::vector<u64> prodM((size_t)n * MWt), consM((size_t)n * MWt), revM((size_t)n * MWt),
+      touchM((size_t)n * MWt), fwdR((size_t)std::max(mi, 1) * Wt), bwdR((size_t)std::max(mi, 1) * Wt),
+      allR((size_t)std::max(mi, 1) * Wt), nbrR((size_t)n * Wt), revb(Wt), zob(n);
+  std::vector<int32_t> Sint((size_t)std::max(mi, 1) * n);
+  for (int k = 0; k < mi; ++k) {
+    const int row = N->int_row[k];
+    for (int r = 0; r < n; ++r) {
+      const int32_t s = N->S[(size_t)row * n + r];
+      Sint[(size_t)k * n + r] = s;
+      if (s == 0) continue;
+      const u64 mb = 1ull << (k & 63), rb = 1ull << (r & 63);
+      const int mq = k >> 6, rw = r >> 6;
+      touchM[(size_t)r * MWt + mq] |= mb;
+      allR[(size_t)k * Wt + rw] |= rb;
+      if (N->rev[r]) {
+        revM[(size_t)r * MWt + mq] |= mb;
+        fwdR[(size_t)k * Wt + rw] |= rb;
+        bwdR[(size_t)k * Wt + rw] |= rb;
+      } else if (s > 0) {
+        prodM[(size_t)r * MWt + mq] |= mb;
+        bwdR[(size_t)k * Wt + rw] |= rb;   // a producer balances a consumed metabolite
+      } else {
+        consM[(size_t)r * MWt + mq] |= mb;
+        fwdR[(size_t)k * Wt + rw] |= rb;   // a consumer balances a produced metabolite
+      }
+    }
+  }
+  for (int r = 0; r < n; ++r) {
+    if (N->rev[r]) revb[r >> 6] |= 1ull << (r & 63);
+    for (int q = 0; q < MWt; ++q) {
+      u64 bits = touchM[(size_t)r * MWt + q];
+      while (bits) {
+        const int k = q * 64 + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        for (int w = 0; w < Wt; ++w) nbrR[(size_t)r * Wt + w] |= allR[(size_t)k * Wt + w];
+      }
+    }
+  }
+  u64 st = 0x5EEDF00DCAFEull;
+  for (int r = 0; r < n; ++r) zob[r] = splitmix64(st);
+
+  // one device blob
+  struct Part { const void *src; size_t bytes; size_t off; };
+  std::vector<Part> parts = {
+      {prodM.data(), prodM.size() * 8, 0}, {consM.data(), consM.size() * 8, 0},
+      {revM.data(), revM.size() * 8, 0},   {touchM.data(), touchM.size() * 8, 0},
+      {fwdR.data(), fwdR.size() * 8, 0},   {bwdR.data(), bwdR.size() * 8, 0},
+      {allR.data(), allR.size() * 8, 0},   {nbrR.data(), nbrR.size() * 8, 0},
+      {revb.data(), revb.size() * 8, 0},   {Sint.data(), Sint.size() * 4, 0},
+      {zob.data(), zob.size() * 8, 0}};
+  size_t total = 0;
+  for (auto &p : parts) { p.off = total; total += align256(p.bytes); }
+  hipError_t e = hipMalloc(&N->blob, total);
+  if (e != hipSuccess) {
+    delete N;
+    return fail(EFM_EDEVICE, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
+  }
+  for (auto &p : parts) {
+    e = hipMemcpy((char *)N->blob + p.off, p.src, p.bytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(N->blob);
+      delete N;
+      return fail(EFM_EDEVICE, "hipMemcpy failed: %s", hipGetErrorString(e));
+    }
+  }
+  auto at = [&](int i) { return (const u64 *)((char *)N->blob + parts[i].off); };
+  efm::DevNet &d = N->dn;
+  d.n = n; d.mi = mi; d.Wt = Wt; d.MWt = MWt;
+  d.rxn_prodM = at(0); d.rxn_consM = at(1); d.rxn_revM = at(2); d.rxn_touchM = at(3);
+  d.met_fwdR = at(4); d.met_bwdR = at(5); d.met_allR = at(6); d.rxn_nbrR = at(7);
+  d.rev_bits = at(8);
+  d.Sint = (const int32_t *)((char *)N->blob + parts[9].off);
+  d.zob = at(10);
+  *out = N;
+  return EFM_OK;
+}
+
+efm_status efm_network_destroy(efm_network *net) {
+  if (!net) return EFM_OK;
+  if (net->blob) (void)hipFree(net->blob);
+  delete net;
+  return EFM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct Layout {
+  int64_t ucap, fcap, ecap, tcap;
+  int xwaves;
+  size_t off_counters, off_hist, off_root, off_sx, off_fa_keys, off_fa_hash, off_fb_keys, off_fb_hash,
+      off_table, off_surv, off_rankq, off_exactq, off_sel, off_blist, off_blist2, off_fkeys, off_fflux,
+      off_xs, total;
+};
+
+int64_t next_pow2(int64_t x) {
+  int64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+Layout make_layout(const efm_network *N, const efm_enum_opts *o) {
+  Layout L{};
+  L.ucap = (o && o->unique_cap > 0) ? o->unique_cap : ((int64_t)1 << 22);
+  L.ucap = std::max<int64_t>(L.ucap, 64);
+  const int64_t fcapo = (o && o->frontier_cap > 0) ? o->frontier_cap : L.ucap;
+  L.fcap = std::max<int64_t>(1, std::min(fcapo, L.ucap));
+  L.ecap = (o && o->found_cap > 0) ? o->found_cap : ((int64_t)1 << 18);
+  L.tcap = std::max<int64_t>(1024, next_pow2(2 * L.ucap));
+  L.xwaves = 512;
+  const int Wt = N->Wt;
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o2 = off; off += align256(bytes); return o2; };
+  L.off_counters = take(efm::kNumCounters * 8);
+  L.off_hist = take(256 * 4);
+  L.off_root = take((size_t)Wt * 8);
+  L.off_sx = take((size_t)N->n * 4);
+  L.off_fa_keys = take((size_t)Wt * L.fcap * 8);
+  L.off_fa_hash = take((size_t)L.fcap * 8);
+  L.off_fb_keys = take((size_t)Wt * L.fcap * 8);
+  L.off_fb_hash = take((size_t)L.fcap * 8);
+  L.off_table = take((size_t)L.tcap * 8);
+  L.off_surv = take((size_t)L.ucap * 8);
+  L.off_rankq = take((size_t)L.ucap * 8);
+  L.off_exactq = take((size_t)L.ucap * 8);
+  L.off_sel = take((size_t)L.ucap);
+  L.off_blist = take((size_t)L.ucap * 4);
+  L.off_blist2 = take((size_t)L.ucap * 4);
+  L.off_fkeys = take((size_t)Wt * L.ecap * 8);
+  L.off_fflux = take((size_t)L.ecap * efm::kMaxDepth * 8);
+  L.off_xs = take((size_t)L.xwaves * std::max(N->mi, 1) * 64 * sizeof(efm::i128));
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+efm_status efm_workspace_query(const efm_network *net, const efm_enum_opts *opts, size_t *bytes) {
+  if (!net || !bytes) return fail(EFM_EINVAL, "null pointer");
+  *bytes = make_layout(net, opts).total;
+  return EFM_OK;
+}
+
+efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_opts *opts,
+                         efm_result **out) {
+  if (!N || !out) return fail(EFM_EINVAL, "null pointer");
+  if (target < 0 || target >= N->m || !N->ext[target])
+    return fail(EFM_EINVAL, "target %d is not an external metabolite", target);
+  efm_enum_opts o{};
+  if (opts) o = *opts;
+  const int n = N->n, Wt = N->Wt;
+  std::vector<u64> root(Wt, 0);
+  std::vector<int32_t> sx(n);
+  int nroot = 0;
+  for (int r = 0; r < n; ++r) {
+    const int32_t s = N->S[(size_t)target * n + r];
+    sx[r] = s;
+    if (s > 0 || (s < 0 && N->rev[r])) { root[r >> 6] |= 1ull << (r & 63); nroot++; }
+  }
+  if (nroot == 0) return fail(EFM_EINVAL, "no reaction can produce target %d", target);
+  int D = o.depth_cap > 0 ? o.depth_cap : EFM_MAX_DEPTH;
+  D = std::min(D, EFM_MAX_DEPTH);
+  D = std::min(D, n);
+  const Layout Lo = make_layout(N, &o);
+  if (o.workspace && o.workspace_bytes < Lo.total)
+    return fail(EFM_ENOMEM, "workspace of %zu bytes, %zu needed", o.workspace_bytes, Lo.total);
+  const bool timing = (o.flags & EFM_OPT_TIME_KERNELS) != 0;
+  hipStream_t s = (hipStream_t)o.stream;
+
+  efm_status rc = EFM_OK;
+  char *ws = (char *)o.workspace;
+  bool owned = false;
+  efm_result *R = nullptr;
+  hipEvent_t ev[12] = {};
+  std::vector<u64> hc(efm::kNumCounters);
+  std::vector<uint32_t> hh(256);
+  int64_t nparents = 1, nfound = 0;
+  int level = 0;
+  uint32_t status = 0;
+  std::vector<efm_level_stats> stats;
+  efm::DevLevel L{};
+  u64 *fa_keys, *fa_hash, *fb_keys, *fb_hash;
+
+  if (!ws) {
+    HIPCHK(hipMalloc((void **)&ws, Lo.total));
+    owned = true;
+  }
+  if (timing)
+    for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+
+  fa_keys = (u64 *)(ws + Lo.off_fa_keys);
+  fa_hash = (u64 *)(ws + Lo.off_fa_hash);
+  fb_keys = (u64 *)(ws + Lo.off_fb_keys);
+  fb_hash = (u64 *)(ws + Lo.off_fb_hash);
+  L.counters = (u64 *)(ws + Lo.off_counters);
+  L.hist = (uint32_t *)(ws + Lo.off_hist);
+  L.Sx = (const int32_t *)(ws + Lo.off_sx);
+  L.table = (u64 *)(ws + Lo.off_table);
+  L.tmask = (u64)Lo.tcap - 1;
+  L.surv = (u64 *)(ws + Lo.off_surv);
+  L.rankq = (u64 *)(ws + Lo.off_rankq);
+  L.exactq = (u64 *)(ws + Lo.off_exactq);
+  L.ucap = Lo.ucap;
+  L.fcap = Lo.fcap;
+  L.sel = (uint8_t *)(ws + Lo.off_sel);
+  L.fkeys = (u64 *)(ws + Lo.off_fkeys);
+  L.fflux = (int64_t *)(ws + Lo.off_fflux);
+  L.ecap = Lo.ecap;
+  L.xscratch = (efm::i128 *)(ws + Lo.off_xs);
+  L.xwaves = Lo.xwaves;
+  L.depth_cap = D;
+  L.debug_prime = (o.flags & EFM_OPT_EXACT_RANK) ? 1 : 0;
+
+  HIPCHK(hipMemcpyAsync(ws + Lo.off_root, root.data(), Wt * 8, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(ws + Lo.off_sx, sx.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+  HIPCHK(efm::launch_clear(L.table, (size_t)Lo.tcap, s));
+  HIPCHK(hipMemsetAsync(L.counters, 0, efm::kNumCounters * 8, s));
+  for (int w = 0; w < Wt; ++w) HIPCHK(hipMemsetAsync(fa_keys + (size_t)w * Lo.fcap, 0, 8, s));
+  HIPCHK(hipMemsetAsync(fa_hash, 0, 8, s));
+
+  while (nparents > 0 && level < D) {
+    // per-level counters (the found count persists)
+    HIPCHK(hipMemsetAsync(L.counters, 0, efm::kFound * 8, s));
+    HIPCHK(hipMemsetAsync(L.counters + efm::kChildren, 0, (efm::kNumCounters - efm::kChildren) * 8, s));
+    L.keys = fa_keys;
+    L.hash = fa_hash;
+    L.nkeys = fb_keys;
+    L.nhash = fb_hash;
+    L.nparents = nparents;
+    L.level = level;
+    L.root_cand = level == 0 ? (const u64 *)(ws + Lo.off_root) : nullptr;
+    L.nfound_prev = nfound;
+    L.blist = (uint32_t *)(ws + Lo.off_blist);
+    L.blist2 = (uint32_t *)(ws + Lo.off_blist2);
+
+    if (timing) HIPCHK(hipEventRecord(ev[0], s));
+    HIPCHK(efm::launch_expand(N->dn, L, s));
+    if (timing) HIPCHK(hipEventRecord(ev[1], s));
+    HIPCHK(efm::launch_rank(N->dn, L, (o.flags & EFM_OPT_NO_PRUNE) ? 0 : 1, s));
+    if (timing) HIPCHK(hipEventRecord(ev[2], s));
+    HIPCHK(efm::launch_exact(N->dn, L, s));
+    if (timing) HIPCHK(hipEventRecord(ev[3], s));
+    HIPCHK(hipMemcpyAsync(hc.data(), L.counters, efm::kNumCounters * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    {
+      const u64 fl = hc[efm::kFlags];
+      if (fl & (efm::kFlagUniqueOverflow | efm::kFlagQueueOverflow)) {
+        rc = fail(EFM_ENOMEM, "level %d: more than unique_cap=%lld distinct children; raise unique_cap",
+                  level + 1, (long long)Lo.ucap);
+        goto done;
+      }
+      if (fl & efm::kFlagFoundOverflow) {
+        rc = fail(EFM_ENOMEM, "more than found_cap=%lld pathways; raise found_cap", (long long)Lo.ecap);
+        goto done;
+      }
+      if (fl & efm::kFlagIntOverflow) {
+        rc = fail(EFM_EOVERFLOW, "level %d: exact arithmetic exceeded 128-bit headroom", level + 1);
+        goto done;
+      }
+      if (fl & efm::kFlagDepthCapped) status |= EFM_DEPTH_CAPPED;
+    }
+    const int64_t nsurv = (int64_t)hc[efm::kSurv];
+    int use_sel = 0;
+    float ms_sel = 0.f;
+    if (o.frontier_cap > 0 && nsurv > o.frontier_cap) {
+      if (timing) HIPCHK(hipEventRecord(ev[4], s));
+      use_sel = 1;
+      status |= EFM_FRONTIER_TRUNCATED;
+      HIPCHK(hipMemsetAsync(L.sel, 0, (size_t)nsurv, s));
+      int64_t needed = o.frontier_cap, nb = nsurv;
+      int first = 1;
+      for (int byte = (n - 1) / 8; byte >= 0; --byte) {
+        HIPCHK(hipMemsetAsync(L.hist, 0, 256 * 4, s));
+        HIPCHK(efm::launch_select_hist(N->dn, L, byte, first, nb, s));
+        HIPCHK(hipMemcpyAsync(hh.data(), L.hist, 256 * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int64_t cum = 0;
+        int v = 0;
+        for (v = 0; v < 256; ++v) {
+          if (cum + hh[v] >= needed) break;
+          cum += hh[v];
+        }
+        const int64_t remaining = needed - cum;
+        const int all_sel = (int64_t)hh[v] == remaining;
+        HIPCHK(hipMemsetAsync(L.counters + efm::kBoundary, 0, 8, s));
+        HIPCHK(efm::launch_select_split(N->dn, L, byte, first, nb, (uint32_t)v, all_sel, s));
+        if (all_sel) break;
+        needed = remaining;
+        nb = hh[v];
+        std::swap(L.blist, L.blist2);
+        first = 0;
+      }
+      if (timing) HIPCHK(hipEventRecord(ev[5], s));
+    }
+    if (timing) HIPCHK(hipEventRecord(ev[6], s));
+    HIPCHK(efm::launch_materialize(N->dn, L, use_sel, s));
+    if (timing) {
+      HIPCHK(hipEventRecord(ev[7], s));
+      HIPCHK(hipEventSynchronize(ev[7]));
+    }
+    efm_level_stats st{};
+    st.parents = nparents;
+    st.children = (int64_t)hc[efm::kChildren];
+    st.unique = (int64_t)hc[efm::kUnique];
+    st.row_closed = (int64_t)hc[efm::kRankQ];
+    st.pruned = (int64_t)hc[efm::kPruned];
+    st.independent = (int64_t)hc[efm::kIndep];
+    st.emitted = (int64_t)hc[efm::kEmitted];
+    st.kept = use_sel ? o.frontier_cap : nsurv;
+    if (timing) {
+      float t;
+      HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1])); st.ms_expand = t;
+      HIPCHK(hipEventElapsedTime(&t, ev[1], ev[2])); st.ms_rank = t;
+      HIPCHK(hipEventElapsedTime(&t, ev[2], ev[3])); st.ms_exact = t;
+      if (use_sel) { HIPCHK(hipEventElapsedTime(&t, ev[4], ev[5])); ms_sel = t; }
+      st.ms_select = ms_sel;
+      HIPCHK(hipEventElapsedTime(&t, ev[6], ev[7])); st.ms_materialize = t;
+    }
+    stats.push_back(st);
+    nfound = std::min<int64_t>((int64_t)hc[efm::kFound], Lo.ecap);
+    std::swap(fa_keys, fb_keys);
+    std::swap(fa_hash, fb_hash);
+    nparents = st.kept;
+    level++;
+  }
+  HIPCHK(hipStreamSynchronize(s));
+
+  R = new (std::nothrow) efm_result;
+  if (!R) { rc = fail(EFM_ENOMEM, "host allocation failed"); goto done; }
+  R->W = N->W;
+  R->n = n;
+  R->status = status;
+  R->levels = stats;
+  {
+    const int W = N->W;
+    std::vector<u64> fk((size_t)Wt * std::max<int64_t>(nfound, 1));
+    std::vector<int64_t> ff((size_t)std::max<int64_t>(nfound, 1) * efm::kMaxDepth);
+    for (int w = 0; w < Wt && nfound > 0; ++w)
+      HIPCHK(hipMemcpy(fk.data() + (size_t)w * nfound, L.fkeys + (size_t)w * Lo.ecap, (size_t)nfound * 8,
+                       hipMemcpyDeviceToHost));
+    if (nfound > 0)
+      HIPCHK(hipMemcpy(ff.data(), L.fflux, (size_t)nfound * efm::kMaxDepth * 8, hipMemcpyDeviceToHost));
+    std::vector<int64_t> order(nfound);
+    for (int64_t i = 0; i < nfound; ++i) order[i] = i;
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+      for (int w = Wt - 1; w >= 0; --w) {
+        const u64 x = fk[(size_t)w * nfound + a], y = fk[(size_t)w * nfound + b];
+        if (x != y) return x < y;
+      }
+      return false;
+    });
+    R->count = nfound;
+    R->keys.assign((size_t)nfound * W, 0);
+    R->flux.assign((size_t)nfound * n, 0);
+    for (int64_t i = 0; i < nfound; ++i) {
+      const int64_t src = order[i];
+      int j = 0;
+      for (int w = 0; w < Wt; ++w) {
+        u64 bits = fk[(size_t)w * nfound + src];
+        if (w < W) R->keys[(size_t)i * W + w] = bits;
+        while (bits) {
+          const int r = w * 64 + __builtin_ctzll(bits);
+          bits &= bits - 1;
+          R->flux[(size_t)i * n + r] = ff[(size_t)src * efm::kMaxDepth + j];
+          j++;
+        }
+      }
+    }
+  }
+
+done:
+  if (timing)
+    for (auto &e : ev)
+      if (e) (void)hipEventDestroy(e);
+  if (owned && ws) {
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(ws);
+  }
+  if (rc != EFM_OK) {
+    delete R;
+    return rc;
+  }
+  *out = R;
+  return EFM_OK;
+}
+
+efm_status efm_result_info(const efm_result *res, int64_t *n_pathways, int32_t *words, uint32_t *status_flags,
+                           int32_t *n_levels) {
+  if (!res) return fail(EFM_EINVAL, "null result");
+  if (n_pathways) *n_pathways = res->count;
+  if (words) *words = res->W;
+  if (status_flags) *status_flags = res->status;
+  if (n_levels) *n_levels = (int32_t)res->levels.size();
+  return EFM_OK;
+}
+
+efm_status efm_result_stats(const efm_result *res, efm_level_stats *stats, int32_t max_levels) {
+  if (!res || (!stats && max_levels > 0)) return fail(EFM_EINVAL, "null pointer");
+  const int k = std::min<int>(max_levels, (int)res->levels.size());
+  for (int i = 0; i < k; ++i) stats[i] = res->levels[i];
+  return EFM_OK;
+}
+
+efm_status efm_result_bitsets(const efm_result *res, uint64_t *dst, int64_t dst_words) {
+  if (!res || (!dst && res->count > 0)) return fail(EFM_EINVAL, "null pointer");
+  if (dst_words < res->count * res->W)
+    return fail(EFM_EINVAL, "buffer of %lld words, %lld needed", (long long)dst_words,
+                (long long)(res->count * res->W));
+  if (res->count) memcpy(dst, res->keys.data(), res->keys.size() * 8);
+  return EFM_OK;
+}
+
+efm_status efm_result_fluxes(const efm_result *res, int64_t *dst, int64_t dst_len) {
+  if (!res || (!dst && res->count > 0)) return fail(EFM_EINVAL, "null pointer");
+  if (dst_len < res->count * res->n)
+    return fail(EFM_EINVAL, "buffer of %lld entries, %lld needed", (long long)dst_len,
+                (long long)(res->count * res->n));
+  if (res->count) memcpy(dst, res->flux.data(), res->flux.size() * 8);
+  return EFM_OK;
+}
+
+efm_status efm_result_destroy(efm_result *res) {
+  delete res;
+  return EFM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,111 @@
+// efm_internal.h -- shared declarations of the gfx950 library (host and device).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace efm {
+
+typedef unsigned long long u64;
+typedef __int128 i128;
+
+// Modulus of the fast rank test: the Mersenne prime 2^31 - 1.  A "dependent"
+// verdict is always confirmed in exact integer arithmetic, and "independent"
+// modulo a prime implies independent over the rationals, so the prime only
+// decides which children take the exact path.
+constexpr uint32_t kPrime = 2147483647u;
+constexpr int kMaxDepth = 64;      // support sizes handled (a wave holds one column per lane)
+constexpr int kPruneMax = 8192;    // found pathways scanned by the minimality prune
+
+// Counter slots (u64) in device memory, reset per level except kFound.
+enum Counter {
+  kSurv = 0,       // survivors (refs) appended this level
+  kRankQ,          // row-closed children queued for the rank test
+  kExactQ,         // children queued for the exact test
+  kFound,          // pathways in the found list (all levels)
+  kChildren,       // children generated
+  kUnique,         // distinct children
+  kPruned,         // row-closed children removed by the found-set prune
+  kEmitted,        // pathways found this level
+  kNext,           // members written to the next frontier
+  kIndep,          // distinct children with independent columns
+  kFlags,          // EFM_* flags and overflow bits below
+  kBoundary,       // radix-select boundary list length
+  kNumCounters
+};
+enum FlagBits : u64 {
+  kFlagDepthCapped = 1ull,
+  kFlagUniqueOverflow = 1ull << 8,
+  kFlagFoundOverflow = 1ull << 9,
+  kFlagIntOverflow = 1ull << 10,
+  kFlagQueueOverflow = 1ull << 11,
+};
+
+// Device tables of one network.  Masks are padded to the template widths
+// Wt (reaction words) and MWt (internal-metabolite words).
+struct DevNet {
+  int n;            // reactions
+  int mi;           // internal metabolites
+  int Wt, MWt;      // padded widths
+  const u64 *rxn_prodM;   // [n][MWt] internal metabolites an irreversible reaction produces
+  const u64 *rxn_consM;   // [n][MWt] ... consumes
+  const u64 *rxn_revM;    // [n][MWt] internal metabolites a reversible reaction touches
+  const u64 *rxn_touchM;  // [n][MWt] all internal metabolites a reaction touches
+  const u64 *met_fwdR;    // [mi][Wt] candidates when only irreversible producers touch i
+  const u64 *met_bwdR;    // [mi][Wt] candidates when only irreversible consumers touch i
+  const u64 *met_allR;    // [mi][Wt] every reaction touching i
+  const u64 *rxn_nbrR;    // [n][Wt] reactions sharing an internal metabolite with r
+  const u64 *rev_bits;    // [Wt]
+  const int32_t *Sint;    // [mi][n] dense internal rows
+  const u64 *zob;         // [n] Zobrist keys
+};
+
+// Per-enumeration device state.
+struct DevLevel {
+  // frontier being expanded
+  const u64 *keys;        // SoA [Wt][fcap]
+  const u64 *hash;        // [fcap]
+  int64_t nparents;
+  int64_t fcap;
+  int level;              // members of the frontier have `level` reactions
+  int depth_cap;
+  // children
+  u64 *table;             // [tcap] open addressing, level-tagged entries
+  u64 tmask;              // tcap - 1
+  u64 *surv;              // [ucap] refs of independent children
+  u64 *rankq;             // [ucap] refs of row-closed children
+  u64 *exactq;            // [ucap] refs needing exact arithmetic
+  int64_t ucap;
+  // next frontier
+  u64 *nkeys;             // SoA [Wt][fcap]
+  u64 *nhash;
+  // found pathways
+  u64 *fkeys;             // SoA [Wt][ecap]
+  int64_t *fflux;         // [ecap][kMaxDepth], value of the j-th reaction of the key
+  int64_t ecap;
+  int64_t nfound_prev;    // found pathways from earlier levels (prune scope)
+  // target row
+  const int32_t *Sx;      // [n]
+  // truncation
+  uint8_t *sel;           // [ucap] 0 rejected, 1 selected, 2 boundary
+  uint32_t *blist;        // [ucap] boundary indices
+  uint32_t *blist2;
+  uint32_t *hist;         // [256]
+  u64 *counters;
+  i128 *xscratch;         // exact kernel scratch: [xwaves][mi * kMaxDepth]
+  int xwaves;
+  const u64 *root_cand;   // level 0: candidate reactions of the empty pathway
+  int debug_prime;
+};
+
+// kernel launchers (efm_kernels.hip)
+hipError_t launch_expand(const DevNet &net, const DevLevel &L, hipStream_t s);
+hipError_t launch_rank(const DevNet &net, const DevLevel &L, int prune, hipStream_t s);
+hipError_t launch_exact(const DevNet &net, const DevLevel &L, hipStream_t s);
+hipError_t launch_materialize(const DevNet &net, const DevLevel &L, int use_sel, hipStream_t s);
+hipError_t launch_select_hist(const DevNet &net, const DevLevel &L, int byte, int first, int64_t nb,
+                              hipStream_t s);
+hipError_t launch_select_split(const DevNet &net, const DevLevel &L, int byte, int first, int64_t nb,
+                               uint32_t digit, int all_sel, hipStream_t s);
+hipError_t launch_clear(u64 *p, size_t n, hipStream_t s);
+
+}  // namespace efm

@@ -207,24 +207,25 @@ def genome(seed: int) -> Network:
     return powerlaw_network(rng, 400, 600, 40, rev_frac=0.3, name=f"genome/{seed}")
 
 
-def batch_sizes(seed: int) -> tuple[int, int]:
-    """(m_int, n_int) of one batch network, log-uniform; redrawn from the same
-    stream while the reactions have too few slots to touch every metabolite."""
-    rng = np.random.default_rng(seed)
+def batch_member(i: int) -> Network:
+    """Batch network i (seed 100000 + i): m_int log-uniform in [10, 80] and n_int
+    log-uniform in [15, 120], drawn independently, then the central-shape
+    generator.  A size pair whose networks fail to connect within 200 draws, or
+    with too few reaction slots to touch every metabolite (3 n < m), is replaced
+    by the next pair from the same stream."""
+    rng = np.random.default_rng(100000 + i)
     while True:
         m = _round_half_up(math.exp(rng.uniform(math.log(10), math.log(80))))
         n = _round_half_up(math.exp(rng.uniform(math.log(15), math.log(120))))
-        if 3 * n >= m:
-            return m, n, rng
-
-
-def batch_member(i: int) -> Network:
-    seed = 100000 + i
-    m, n, rng = batch_sizes(seed)
-    n_ex = max(2, _round_half_up(m / 6))
-    n_hub = 5 if m >= 30 else max(1, m // 6)
-    return uniform_network(rng, m, n, n_ex, rev_frac=0.2, coef=COEF_CENTRAL, n_hub=n_hub,
-                           name=f"batch/{i}")
+        if 3 * n < m:
+            continue
+        n_ex = max(2, _round_half_up(m / 6))
+        n_hub = 5 if m >= 30 else max(1, m // 6)
+        try:
+            return uniform_network(rng, m, n, n_ex, rev_frac=0.2, coef=COEF_CENTRAL, n_hub=n_hub,
+                                   name=f"batch/{i}", max_attempts=200)
+        except RuntimeError:
+            continue
 
 
 SHAPES = {"tiny": tiny, "central": central, "genome": genome}
