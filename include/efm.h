@@ -75,6 +75,8 @@ typedef struct {
 #define EFM_OPT_NO_PRUNE 1u      /* skip the found-set minimality prune (result unchanged) */
 #define EFM_OPT_EXACT_RANK 2u    /* decide every rank test in exact integer arithmetic instead of
                                     modulo a prime first (slower; result unchanged) */
+#define EFM_OPT_NO_GF2 8u        /* skip the modulo-2 independence certificate, so every undecided
+                                    rank test runs modulo the prime (result unchanged) */
 #define EFM_OPT_TIME_KERNELS 4u  /* record HIP events around every kernel launch on the stream and
                                     report per-level kernel times in efm_level_stats */
 

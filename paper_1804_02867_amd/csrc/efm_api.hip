@@ -112,7 +112,7 @@ efm_status efm_network_create(int32_t n_met, int32_t n_rxn, const int32_t *S, co
 
   // host tables
   std::vector<u64> prodM((size_t)n * MWt), consM((size_t)n * MWt), revM((size_t)n * MWt),
-      touchM((size_t)n * MWt), fwdR((size_t)std::max(mi, 1) * Wt), bwdR((size_t)std::max(mi, 1) * Wt),
+      touchM((size_t)n * MWt), oddM((size_t)n * MWt), fwdR((size_t)std::max(mi, 1) * Wt), bwdR((size_t)std::max(mi, 1) * Wt),
       allR((size_t)std::max(mi, 1) * Wt), nbrR((size_t)n * Wt), revb(Wt), zob(n);
   std::vector<int32_t> Sint((size_t)std::max(mi, 1) * n);
   for (int k = 0; k < mi; ++k) {
@@ -124,6 +124,7 @@ efm_status efm_network_create(int32_t n_met, int32_t n_rxn, const int32_t *S, co
       const u64 mb = 1ull << (k & 63), rb = 1ull << (r & 63);
       const int mq = k >> 6, rw = r >> 6;
       touchM[(size_t)r * MWt + mq] |= mb;
+      if (s & 1) oddM[(size_t)r * MWt + mq] |= mb;
       allR[(size_t)k * Wt + rw] |= rb;
       if (N->rev[r]) {
         revM[(size_t)r * MWt + mq] |= mb;
@@ -149,6 +150,21 @@ efm_status efm_network_create(int32_t n_met, int32_t n_rxn, const int32_t *S, co
       }
     }
   }
+  // per-reaction column entries for the rank test (internal metabolite, coefficient)
+  std::vector<uint32_t> ent((size_t)n * efm::kMaxEnt, 0xFFFF0000u);
+  std::vector<int32_t> nnz(n, 0);
+  for (int r = 0; r < n; ++r) {
+    int c = 0;
+    bool fits = true;
+    for (int k = 0; k < mi; ++k) {
+      const int32_t v = Sint[(size_t)k * n + r];
+      if (v == 0) continue;
+      if (c >= efm::kMaxEnt || v < -32768 || v > 32767 || k > 0xFFFE) { fits = false; continue; }
+      ent[(size_t)r * efm::kMaxEnt + c] = ((uint32_t)k << 16) | ((uint32_t)v & 0xFFFFu);
+      c++;
+    }
+    nnz[r] = fits ? c : -1;
+  }
   u64 st = 0x5EEDF00DCAFEull;
   for (int r = 0; r < n; ++r) zob[r] = splitmix64(st);
 
@@ -160,7 +176,8 @@ efm_status efm_network_create(int32_t n_met, int32_t n_rxn, const int32_t *S, co
       {fwdR.data(), fwdR.size() * 8, 0},   {bwdR.data(), bwdR.size() * 8, 0},
       {allR.data(), allR.size() * 8, 0},   {nbrR.data(), nbrR.size() * 8, 0},
       {revb.data(), revb.size() * 8, 0},   {Sint.data(), Sint.size() * 4, 0},
-      {zob.data(), zob.size() * 8, 0}};
+      {zob.data(), zob.size() * 8, 0},     {ent.data(), ent.size() * 4, 0},
+      {nnz.data(), nnz.size() * 4, 0},     {oddM.data(), oddM.size() * 8, 0}};
   size_t total = 0;
   for (auto &p : parts) { p.off = total; total += align256(p.bytes); }
   hipError_t e = hipMalloc(&N->blob, total);
@@ -184,6 +201,9 @@ efm_status efm_network_create(int32_t n_met, int32_t n_rxn, const int32_t *S, co
   d.rev_bits = at(8);
   d.Sint = (const int32_t *)((char *)N->blob + parts[9].off);
   d.zob = at(10);
+  d.rxn_ent = (const uint32_t *)((char *)N->blob + parts[11].off);
+  d.rxn_nnz = (const int32_t *)((char *)N->blob + parts[12].off);
+  d.rxn_oddM = at(13);
   *out = N;
   return EFM_OK;
 }
@@ -202,8 +222,8 @@ namespace {
 struct Layout {
   int64_t ucap, fcap, ecap, tcap;
   int xwaves;
-  size_t off_counters, off_hist, off_root, off_sx, off_fa_keys, off_fa_hash, off_fb_keys, off_fb_hash,
-      off_table, off_surv, off_rankq, off_exactq, off_sel, off_blist, off_blist2, off_fkeys, off_fflux,
+  size_t off_counters, off_hist, off_selst, off_root, off_sx, off_fa_keys, off_fa_hash, off_fb_keys, off_fb_hash,
+      off_table, off_surv, off_rankq, off_exactq, off_sel, off_skey, off_fkeys, off_fflux,
       off_xs, total;
 };
 
@@ -225,8 +245,9 @@ Layout make_layout(const efm_network *N, const efm_enum_opts *o) {
   const int Wt = N->Wt;
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o2 = off; off += align256(bytes); return o2; };
-  L.off_counters = take(efm::kNumCounters * 8);
-  L.off_hist = take(256 * 4);
+  L.off_counters = take(efm::kNumCounters * efm::kCounterStride * 8);
+  L.off_hist = take(2 * 256 * 4);
+  L.off_selst = take(2 * sizeof(efm::SelState));
   L.off_root = take((size_t)Wt * 8);
   L.off_sx = take((size_t)N->n * 4);
   L.off_fa_keys = take((size_t)Wt * L.fcap * 8);
@@ -238,8 +259,7 @@ Layout make_layout(const efm_network *N, const efm_enum_opts *o) {
   L.off_rankq = take((size_t)L.ucap * 8);
   L.off_exactq = take((size_t)L.ucap * 8);
   L.off_sel = take((size_t)L.ucap);
-  L.off_blist = take((size_t)L.ucap * 4);
-  L.off_blist2 = take((size_t)L.ucap * 4);
+  L.off_skey = take((size_t)L.ucap * 8);
   L.off_fkeys = take((size_t)Wt * L.ecap * 8);
   L.off_fflux = take((size_t)L.ecap * efm::kMaxDepth * 8);
   L.off_xs = take((size_t)L.xwaves * std::max(N->mi, 1) * 64 * sizeof(efm::i128));
@@ -288,10 +308,12 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
   bool owned = false;
   efm_result *R = nullptr;
   hipEvent_t ev[12] = {};
-  std::vector<u64> hc(efm::kNumCounters);
-  std::vector<uint32_t> hh(256);
+  std::vector<u64> hcs((size_t)efm::kNumCounters * efm::kCounterStride), hc(efm::kNumCounters);
+  u64 found_host = 0;
+  efm::SelState sel_init{};
   int64_t nparents = 1, nfound = 0;
-  int level = 0;
+  int level = 0, next_tag = 1;
+  double branching = 1.0;
   uint32_t status = 0;
   std::vector<efm_level_stats> stats;
   efm::DevLevel L{};
@@ -310,15 +332,16 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
   fb_hash = (u64 *)(ws + Lo.off_fb_hash);
   L.counters = (u64 *)(ws + Lo.off_counters);
   L.hist = (uint32_t *)(ws + Lo.off_hist);
+  L.selst = (efm::SelState *)(ws + Lo.off_selst);
   L.Sx = (const int32_t *)(ws + Lo.off_sx);
   L.table = (u64 *)(ws + Lo.off_table);
-  L.tmask = (u64)Lo.tcap - 1;
   L.surv = (u64 *)(ws + Lo.off_surv);
   L.rankq = (u64 *)(ws + Lo.off_rankq);
   L.exactq = (u64 *)(ws + Lo.off_exactq);
   L.ucap = Lo.ucap;
   L.fcap = Lo.fcap;
   L.sel = (uint8_t *)(ws + Lo.off_sel);
+  L.skey = (u64 *)(ws + Lo.off_skey);
   L.fkeys = (u64 *)(ws + Lo.off_fkeys);
   L.fflux = (int64_t *)(ws + Lo.off_fflux);
   L.ecap = Lo.ecap;
@@ -326,18 +349,20 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
   L.xwaves = Lo.xwaves;
   L.depth_cap = D;
   L.debug_prime = (o.flags & EFM_OPT_EXACT_RANK) ? 1 : 0;
+  L.no_gf2 = (o.flags & EFM_OPT_NO_GF2) ? 1 : 0;
 
   HIPCHK(hipMemcpyAsync(ws + Lo.off_root, root.data(), Wt * 8, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ws + Lo.off_sx, sx.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
   HIPCHK(efm::launch_clear(L.table, (size_t)Lo.tcap, s));
-  HIPCHK(hipMemsetAsync(L.counters, 0, efm::kNumCounters * 8, s));
+  HIPCHK(hipMemsetAsync(L.counters, 0, efm::kNumCounters * efm::kCounterStride * 8, s));
   for (int w = 0; w < Wt; ++w) HIPCHK(hipMemsetAsync(fa_keys + (size_t)w * Lo.fcap, 0, 8, s));
   HIPCHK(hipMemsetAsync(fa_hash, 0, 8, s));
 
   while (nparents > 0 && level < D) {
     // per-level counters (the found count persists)
-    HIPCHK(hipMemsetAsync(L.counters, 0, efm::kFound * 8, s));
-    HIPCHK(hipMemsetAsync(L.counters + efm::kChildren, 0, (efm::kNumCounters - efm::kChildren) * 8, s));
+    found_host = (u64)nfound;
+    HIPCHK(hipMemsetAsync(L.counters, 0, efm::kNumCounters * efm::kCounterStride * 8, s));
+    HIPCHK(hipMemcpyAsync(L.counters + efm::cslot(efm::kFound), &found_host, 8, hipMemcpyHostToDevice, s));
     L.keys = fa_keys;
     L.hash = fa_hash;
     L.nkeys = fb_keys;
@@ -346,18 +371,40 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
     L.level = level;
     L.root_cand = level == 0 ? (const u64 *)(ws + Lo.off_root) : nullptr;
     L.nfound_prev = nfound;
-    L.blist = (uint32_t *)(ws + Lo.off_blist);
-    L.blist2 = (uint32_t *)(ws + Lo.off_blist2);
 
-    if (timing) HIPCHK(hipEventRecord(ev[0], s));
-    HIPCHK(efm::launch_expand(N->dn, L, s));
-    if (timing) HIPCHK(hipEventRecord(ev[1], s));
-    HIPCHK(efm::launch_rank(N->dn, L, (o.flags & EFM_OPT_NO_PRUNE) ? 0 : 1, s));
-    if (timing) HIPCHK(hipEventRecord(ev[2], s));
-    HIPCHK(efm::launch_exact(N->dn, L, s));
-    if (timing) HIPCHK(hipEventRecord(ev[3], s));
-    HIPCHK(hipMemcpyAsync(hc.data(), L.counters, efm::kNumCounters * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
+    // table slots for this level: twice the children the previous level's
+    // branching predicts, at least 1024; rerun at full size if that was too few
+    {
+      int64_t est = level == 0 ? nroot : (int64_t)((double)nparents * branching * 1.5) + 1024;
+      int64_t tl = std::max<int64_t>(1024, next_pow2(2 * est));
+      tl = std::min<int64_t>(tl, Lo.tcap);
+      for (int attempt = 0;; ++attempt) {
+        if (next_tag > 127) {
+          HIPCHK(efm::launch_clear(L.table, (size_t)Lo.tcap, s));
+          next_tag = 1;
+        }
+        L.tag = next_tag++;
+        L.tmask = (u64)tl - 1;
+        if (timing) HIPCHK(hipEventRecord(ev[0], s));
+        HIPCHK(efm::launch_expand(N->dn, L, s));
+        if (timing) HIPCHK(hipEventRecord(ev[1], s));
+        HIPCHK(efm::launch_rank(N->dn, L, (o.flags & EFM_OPT_NO_PRUNE) ? 0 : 1, s));
+        if (timing) HIPCHK(hipEventRecord(ev[2], s));
+        HIPCHK(efm::launch_exact(N->dn, L, s));
+        if (timing) HIPCHK(hipEventRecord(ev[3], s));
+        HIPCHK(hipMemcpyAsync(hcs.data(), L.counters, hcs.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int c = 0; c < efm::kNumCounters; ++c) hc[c] = hcs[efm::cslot(c)];
+        const bool table_full = (hc[efm::kFlags] & efm::kFlagUniqueOverflow) != 0;
+        if (!table_full || tl == Lo.tcap) break;
+        // discard this attempt: its emissions sit past nfound and are overwritten
+        tl = Lo.tcap;
+        found_host = (u64)nfound;
+        HIPCHK(hipMemsetAsync(L.counters, 0, efm::kNumCounters * efm::kCounterStride * 8, s));
+        HIPCHK(hipMemcpyAsync(L.counters + efm::cslot(efm::kFound), &found_host, 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+      }
+    }
     {
       const u64 fl = hc[efm::kFlags];
       if (fl & (efm::kFlagUniqueOverflow | efm::kFlagQueueOverflow)) {
@@ -373,7 +420,7 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
         rc = fail(EFM_EOVERFLOW, "level %d: exact arithmetic exceeded 128-bit headroom", level + 1);
         goto done;
       }
-      if (fl & efm::kFlagDepthCapped) status |= EFM_DEPTH_CAPPED;
+      if ((fl & efm::kFlagDepthCapped) || hc[efm::kCapped] > 0) status |= EFM_DEPTH_CAPPED;
     }
     const int64_t nsurv = (int64_t)hc[efm::kSurv];
     int use_sel = 0;
@@ -382,29 +429,16 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
       if (timing) HIPCHK(hipEventRecord(ev[4], s));
       use_sel = 1;
       status |= EFM_FRONTIER_TRUNCATED;
-      HIPCHK(hipMemsetAsync(L.sel, 0, (size_t)nsurv, s));
-      int64_t needed = o.frontier_cap, nb = nsurv;
-      int first = 1;
-      for (int byte = (n - 1) / 8; byte >= 0; --byte) {
-        HIPCHK(hipMemsetAsync(L.hist, 0, 256 * 4, s));
-        HIPCHK(efm::launch_select_hist(N->dn, L, byte, first, nb, s));
-        HIPCHK(hipMemcpyAsync(hh.data(), L.hist, 256 * 4, hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        int64_t cum = 0;
-        int v = 0;
-        for (v = 0; v < 256; ++v) {
-          if (cum + hh[v] >= needed) break;
-          cum += hh[v];
-        }
-        const int64_t remaining = needed - cum;
-        const int all_sel = (int64_t)hh[v] == remaining;
-        HIPCHK(hipMemsetAsync(L.counters + efm::kBoundary, 0, 8, s));
-        HIPCHK(efm::launch_select_split(N->dn, L, byte, first, nb, (uint32_t)v, all_sel, s));
-        if (all_sel) break;
-        needed = remaining;
-        nb = hh[v];
-        std::swap(L.blist, L.blist2);
-        first = 0;
+      HIPCHK(hipMemsetAsync(L.sel, 2, (size_t)nsurv, s));
+      HIPCHK(hipMemsetAsync(L.hist, 0, 2 * 256 * 4, s));
+      sel_init = efm::SelState{};
+      sel_init.needed = o.frontier_cap;
+      sel_init.nb = nsurv;
+      HIPCHK(hipMemcpyAsync(L.selst, &sel_init, sizeof(sel_init), hipMemcpyHostToDevice, s));
+      const int top = (n - 1) / 8;
+      for (int byte = top, pass = 0; byte >= 0; --byte, ++pass) {
+        HIPCHK(efm::launch_select_hist(N->dn, L, byte, byte == top || (byte & 7) == 7, pass, s));
+        HIPCHK(efm::launch_select_split(N->dn, L, byte, pass, s));
       }
       if (timing) HIPCHK(hipEventRecord(ev[5], s));
     }
@@ -434,6 +468,7 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
     }
     stats.push_back(st);
     nfound = std::min<int64_t>((int64_t)hc[efm::kFound], Lo.ecap);
+    if (level > 0 && nparents > 0) branching = std::max(1.0, (double)st.children / (double)nparents);
     std::swap(fa_keys, fb_keys);
     std::swap(fa_hash, fb_hash);
     nparents = st.kept;

@@ -30,8 +30,15 @@ enum Counter {
   kIndep,          // distinct children with independent columns
   kFlags,          // EFM_* flags and overflow bits below
   kBoundary,       // radix-select boundary list length
+  kCapped,         // independent children dropped by the depth cap
   kNumCounters
 };
+// Counters sit 256 bytes apart so that atomics on different counters never share
+// a cache line.
+constexpr int kCounterStride = 32;
+__host__ __device__ inline size_t cslot(int c) { return (size_t)c * kCounterStride; }
+constexpr int kMaxEnt = 16;        // column entries kept in registers by the rank test
+
 enum FlagBits : u64 {
   kFlagDepthCapped = 1ull,
   kFlagUniqueOverflow = 1ull << 8,
@@ -57,6 +64,18 @@ struct DevNet {
   const u64 *rev_bits;    // [Wt]
   const int32_t *Sint;    // [mi][n] dense internal rows
   const u64 *zob;         // [n] Zobrist keys
+  const uint32_t *rxn_ent;  // [n][kMaxEnt] (internal metabolite << 16) | (coefficient & 0xFFFF)
+  const int32_t *rxn_nnz;   // [n] entries, or -1 when they do not fit rxn_ent (use Sint)
+  const u64 *rxn_oddM;      // [n][MWt] internal metabolites where the coefficient is odd
+};
+
+// Radix-selection state in device memory: the digit decisions are taken on the
+// device, so all byte passes are queued without host round trips.
+struct SelState {
+  int64_t needed;     // members still to select
+  int64_t nb;         // members not yet decided
+  uint32_t done;
+  uint32_t pad;
 };
 
 // Per-enumeration device state.
@@ -69,8 +88,9 @@ struct DevLevel {
   int level;              // members of the frontier have `level` reactions
   int depth_cap;
   // children
-  u64 *table;             // [tcap] open addressing, level-tagged entries
-  u64 tmask;              // tcap - 1
+  u64 *table;             // [tcap] open addressing, tagged entries
+  u64 tmask;              // slots used by this level - 1 (a power of two minus one)
+  int tag;                // 1..127, distinct for every expand launch since the last clear
   u64 *surv;              // [ucap] refs of independent children
   u64 *rankq;             // [ucap] refs of row-closed children
   u64 *exactq;            // [ucap] refs needing exact arithmetic
@@ -86,15 +106,16 @@ struct DevLevel {
   // target row
   const int32_t *Sx;      // [n]
   // truncation
-  uint8_t *sel;           // [ucap] 0 rejected, 1 selected, 2 boundary
-  uint32_t *blist;        // [ucap] boundary indices
-  uint32_t *blist2;
-  uint32_t *hist;         // [256]
+  uint8_t *sel;           // [ucap] 0 rejected, 1 selected, 2 undecided
+  u64 *skey;              // [ucap] the key word the current selection byte lies in
+  uint32_t *hist;         // [2][256], by pass parity
+  SelState *selst;        // [2], by pass parity
   u64 *counters;
   i128 *xscratch;         // exact kernel scratch: [xwaves][mi * kMaxDepth]
   int xwaves;
   const u64 *root_cand;   // level 0: candidate reactions of the empty pathway
-  int debug_prime;
+  int debug_prime;         // every rank test goes to exact arithmetic
+  int no_gf2;              // skip the modulo-2 certificate
 };
 
 // kernel launchers (efm_kernels.hip)
@@ -102,10 +123,9 @@ hipError_t launch_expand(const DevNet &net, const DevLevel &L, hipStream_t s);
 hipError_t launch_rank(const DevNet &net, const DevLevel &L, int prune, hipStream_t s);
 hipError_t launch_exact(const DevNet &net, const DevLevel &L, hipStream_t s);
 hipError_t launch_materialize(const DevNet &net, const DevLevel &L, int use_sel, hipStream_t s);
-hipError_t launch_select_hist(const DevNet &net, const DevLevel &L, int byte, int first, int64_t nb,
+hipError_t launch_select_hist(const DevNet &net, const DevLevel &L, int byte, int refill, int pass,
                               hipStream_t s);
-hipError_t launch_select_split(const DevNet &net, const DevLevel &L, int byte, int first, int64_t nb,
-                               uint32_t digit, int all_sel, hipStream_t s);
+hipError_t launch_select_split(const DevNet &net, const DevLevel &L, int byte, int pass, hipStream_t s);
 hipError_t launch_clear(u64 *p, size_t n, hipStream_t s);
 
 }  // namespace efm

@@ -53,6 +53,56 @@ DEVI void wave_count(bool pred, u64 *counter) {
   if (mask != 0 && lane_id() == __ffsll((long long)mask) - 1) atomicAdd(counter, (u64)__popcll(mask));
 }
 
+// Wave-private staging of list appends in LDS (128 entries): one global atomic per
+// flush instead of one per wave and step.  `n` is wave-uniform.
+constexpr int kWaveBuf = 128;
+struct WaveBuf {
+  u64 *lds;
+  int n;
+};
+
+DEVI void wbuf_flush(WaveBuf &b, u64 *list, u64 *counter, int64_t cap, u64 *flags) {
+  if (b.n == 0) return;
+  const int lane = lane_id();
+  __threadfence_block();
+  u64 base = 0;
+  if (lane == 0) base = atomicAdd(counter, (u64)b.n);
+  base = __shfl(base, 0);
+  for (int i = lane; i < b.n; i += 64) {
+    const u64 idx = base + (u64)i;
+    if ((int64_t)idx < cap) list[idx] = b.lds[i];
+    else atomicOr(flags, (u64)kFlagQueueOverflow);
+  }
+  __threadfence_block();
+  b.n = 0;
+}
+
+DEVI void wbuf_push(WaveBuf &b, bool pred, u64 val, u64 *list, u64 *counter, int64_t cap, u64 *flags) {
+  const u64 mask = __ballot(pred);
+  const int cnt = __popcll(mask);
+  if (cnt == 0) return;
+  if (b.n + cnt > kWaveBuf) wbuf_flush(b, list, counter, cap, flags);
+  if (pred) b.lds[b.n + __popcll(mask & lanes_below(lane_id()))] = val;
+  b.n += cnt;
+}
+
+// Block-wide sum of per-thread counts into global counters (end of kernel; every
+// thread of the block must call it).
+template <int NC>
+DEVI void block_counts(u64 (&v)[NC], u64 *counters, const int (&slot)[NC]) {
+  __shared__ u64 acc[NC];
+  if (threadIdx.x < NC) acc[threadIdx.x] = 0;
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    u64 t = v[c];
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if (lane_id() == 0 && t) atomicAdd(&acc[c], t);
+  }
+  __syncthreads();
+  if (threadIdx.x < NC && acc[threadIdx.x]) atomicAdd(&counters[cslot(slot[threadIdx.x])], acc[threadIdx.x]);
+}
+
 DEVI int wave_max_int(int v) {
   for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
   return v;
@@ -169,7 +219,7 @@ DEVI bool table_insert(const DevLevel &L, u64 tag, u64 h, u64 p, int r, const u6
     }
     pos = (pos + 1) & L.tmask;
   }
-  atomicOr(&L.counters[kFlags], (u64)kFlagUniqueOverflow);
+  atomicOr(&L.counters[cslot(kFlags)], (u64)kFlagUniqueOverflow);
   return false;
 }
 
@@ -177,7 +227,7 @@ template <int W, int MW>
 __global__ __launch_bounds__(256) void expand_kernel(DevNet net, DevLevel L) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool live = p < L.nparents;
-  const u64 tag = (u64)(L.level % 127) + 1;
+  const u64 tag = (u64)L.tag;
   const bool keep_indep = L.level + 1 < L.depth_cap;
   u64 P[W], cand[W], T[MW];
   u64 h = 0;
@@ -256,6 +306,10 @@ __global__ __launch_bounds__(256) void expand_kernel(DevNet net, DevLevel L) {
   }
 
   // children: uniform trip count per wave so the ballots stay converged
+  __shared__ u64 stage[2][4][kWaveBuf];
+  const int wib = threadIdx.x >> 6;
+  WaveBuf bsurv{stage[0][wib], 0}, brank{stage[1][wib], 0};
+  u64 n_unique = 0, n_indep = 0, n_capped = 0;
   const int maxc = wave_max_int(ncand);
   for (int it = 0; it < maxc; ++it) {
     const bool act = it < ncand;
@@ -279,35 +333,37 @@ __global__ __launch_bounds__(256) void expand_kernel(DevNet net, DevLevel L) {
       uniq = table_insert<W>(L, tag, h ^ net.zob[r], (u64)p, r, P);
     }
     const u64 ref = ((u64)p << 12) | ((u64)r << 1) | (rc ? 1ull : 0ull);
-    wave_append(uniq && !rc && keep_indep, L.surv, &L.counters[kSurv], ref, L.ucap,
-                &L.counters[kFlags]);
-    wave_append(uniq && rc, L.rankq, &L.counters[kRankQ], ref, L.ucap, &L.counters[kFlags]);
-    wave_count(uniq, &L.counters[kUnique]);
-    wave_count(uniq && !rc, &L.counters[kIndep]);
-    if (__ballot(uniq && !rc && !keep_indep) != 0 && lane_id() == 0)
-      atomicOr(&L.counters[kFlags], (u64)kFlagDepthCapped);
+    wbuf_push(bsurv, uniq && !rc && keep_indep, ref, L.surv, &L.counters[cslot(kSurv)], L.ucap,
+              &L.counters[cslot(kFlags)]);
+    wbuf_push(brank, uniq && rc, ref, L.rankq, &L.counters[cslot(kRankQ)], L.ucap, &L.counters[cslot(kFlags)]);
+    n_unique += uniq ? 1 : 0;
+    n_indep += (uniq && !rc) ? 1 : 0;
+    n_capped += (uniq && !rc && !keep_indep) ? 1 : 0;
   }
-  // generated children
-  int tot = ncand;
-  for (int off = 32; off > 0; off >>= 1) tot += __shfl_xor(tot, off);
-  if (lane_id() == 0 && tot) atomicAdd(&L.counters[kChildren], (u64)tot);
+  wbuf_flush(bsurv, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
+  wbuf_flush(brank, L.rankq, &L.counters[cslot(kRankQ)], L.ucap, &L.counters[cslot(kFlags)]);
+  u64 v[4] = {(u64)ncand, n_unique, n_indep, n_capped};
+  const int slots[4] = {kChildren, kUnique, kIndep, kCapped};
+  block_counts<4>(v, L.counters, slots);
 }
 
 // -------------------------------------------------------------------------- rank
 // One wave per row-closed child Q = P | e_r.  Lane j holds column j (the j-th
-// reaction of Q).  Rows (the internal metabolites P touches) stream through a
-// basis kept in LDS in reduced form; the child is independent once the basis has
-// |Q| rows.
+// reaction of Q) as its few nonzero entries in registers.  Singleton rows are
+// peeled first; the remaining rows then stream through a basis kept in LDS in
+// reduced form, and the child is independent once the basis has as many rows as
+// there are unpeeled columns.
 template <int W, int MW>
 __global__ __launch_bounds__(256) void rank_kernel(DevNet net, DevLevel L, int prune, int kq_max) {
-  extern __shared__ uint32_t lds[];
+  __shared__ u64 stage[2][4][kWaveBuf];
   const int wib = threadIdx.x >> 6;
   const int lane = lane_id();
   const int wpb = blockDim.x >> 6;
-  uint32_t *basis = lds + (size_t)wib * kq_max * 64;
-  const int64_t nitems = min((int64_t)L.counters[kRankQ], L.ucap);
+  const int64_t nitems = min((int64_t)L.counters[cslot(kRankQ)], L.ucap);
   const bool keep_indep = L.level + 1 < L.depth_cap;
   const int64_t nf = min((int64_t)L.nfound_prev, L.ecap);
+  WaveBuf bsurv{stage[0][wib], 0}, bexact{stage[1][wib], 0};
+  u64 n_indep = 0, n_pruned = 0, n_capped = 0;
 
   for (int64_t item = (int64_t)blockIdx.x * wpb + wib; item < nitems; item += (int64_t)gridDim.x * wpb) {
     const u64 ref = L.rankq[item];
@@ -331,7 +387,7 @@ __global__ __launch_bounds__(256) void rank_kernel(DevNet net, DevLevel L, int p
         hit = __ballot(sub) != 0;
       }
       if (hit) {
-        if (lane == 0) atomicAdd(&L.counters[kPruned], 1ull);
+        n_pruned += lane == 0 ? 1 : 0;
         continue;
       }
     }
@@ -340,54 +396,171 @@ __global__ __launch_bounds__(256) void rank_kernel(DevNet net, DevLevel L, int p
 #pragma unroll
     for (int w = 0; w < W; ++w) kq += __popcll(Q[w]);
     const int col = lane < kq ? select_bit<W>(Q, lane) : -1;
+    u64 tm[MW];
+#pragma unroll
+    for (int q = 0; q < MW; ++q) tm[q] = col >= 0 ? net.rxn_touchM[(int64_t)col * MW + q] : 0ull;
+
+    // Singleton peeling: a row that only one live column touches forces that
+    // column's flux to zero, so column and row leave the matrix and the rank
+    // drops by exactly one.  Q is independent iff what remains is, and it is
+    // independent outright once r's column is peeled (P is independent).
+    bool alive = col >= 0;
+    while (true) {
+      u64 once[MW], multi[MW];
+#pragma unroll
+      for (int q = 0; q < MW; ++q) { once[q] = alive ? tm[q] : 0ull; multi[q] = 0ull; }
+      for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int q = 0; q < MW; ++q) {
+          const u64 o2 = __shfl_xor(once[q], off), m2 = __shfl_xor(multi[q], off);
+          multi[q] = multi[q] | m2 | (once[q] & o2);
+          once[q] = (once[q] | o2) & ~multi[q];
+        }
+      }
+      u64 hit = 0;
+#pragma unroll
+      for (int q = 0; q < MW; ++q) hit |= tm[q] & once[q];
+      const bool peel = alive && hit != 0;
+      if (__ballot(peel) == 0) break;
+      alive = alive && !peel;
+    }
+    const bool r_alive = __ballot(alive && col == r) != 0;
+    const int ncore = __popcll(__ballot(alive));
     u64 T[MW];
 #pragma unroll
-    for (int q = 0; q < MW; ++q) T[q] = wave_or(col >= 0 ? net.rxn_touchM[(int64_t)col * MW + q] : 0ull);
+    for (int q = 0; q < MW; ++q) T[q] = wave_or(alive ? tm[q] : 0ull);
+    int nrows = 0;
+#pragma unroll
+    for (int q = 0; q < MW; ++q) nrows += __popcll(T[q]);
 
-    int nb = 0;
-    int pcreg = 0;                 // lane b holds the pivot column of basis row b
-    bool indep = false;
-    if (!L.debug_prime) {
+    bool indep = !r_alive;
+    if (!L.debug_prime && !L.no_gf2 && r_alive && nrows >= ncore) {
+      // GF(2) certificate: columns independent modulo 2 are independent over the
+      // rationals.  Lane b holds, for the core row q*64+b, the bit mask of the
+      // columns whose coefficient there is odd; XOR elimination over the columns.
+      u64 om[MW], rowm[MW];
+      bool used[MW];
+#pragma unroll
+      for (int q = 0; q < MW; ++q) {
+        om[q] = alive ? net.rxn_oddM[(int64_t)col * MW + q] : 0ull;
+        rowm[q] = 0;
+        used[q] = false;
+        u64 bits = T[q];
+        while (bits) {
+          const int b = __builtin_ctzll(bits);
+          bits &= bits - 1;
+          const u64 m = __ballot((om[q] >> b) & 1ull);
+          if (lane == b) rowm[q] = m;
+        }
+      }
+      u64 cols = __ballot(alive);
+      bool ok = true;
+      while (cols) {
+        const int c = __ffsll((long long)cols) - 1;
+        cols &= cols - 1;
+        int pq = -1, pl = -1;
+#pragma unroll
+        for (int q = 0; q < MW; ++q) {
+          if (pq < 0) {
+            const u64 cand = __ballot(!used[q] && ((rowm[q] >> c) & 1ull));
+            if (cand) { pq = q; pl = __ffsll((long long)cand) - 1; }
+          }
+        }
+        if (pq < 0) { ok = false; break; }
+        u64 prow = 0;
+#pragma unroll
+        for (int q = 0; q < MW; ++q) {
+          if (q == pq) {
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)rowm[q], pl);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(rowm[q] >> 32), pl);
+            prow = ((u64)hi << 32) | lo;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < MW; ++q) {
+          const bool me = (q == pq) && (lane == pl);
+          if (!me && ((rowm[q] >> c) & 1ull)) rowm[q] ^= prow;
+          if (me) used[q] = true;
+        }
+      }
+      indep = ok;
+    }
+    if (!L.debug_prime && r_alive && nrows >= ncore && !indep) {
+      // this lane's column entries
+      uint32_t ent[kMaxEnt];
+      int nnz = alive ? net.rxn_nnz[col] : 0;
+      const bool dense = nnz < 0;
+#pragma unroll
+      for (int e = 0; e < kMaxEnt; ++e) ent[e] = (e < nnz) ? net.rxn_ent[(int64_t)col * kMaxEnt + e] : 0xFFFF0000u;
+      // The basis lives in registers (lane j holds column j of every basis row) in
+      // reduced row-echelon form without normalisation: row b has a nonzero pivot
+      // value d_b in its pivot column and every other row has a 0 there.  A new
+      // row x0 is reduced fraction-free, x <- d_b x - (sigma f_b) row_b over the
+      // pivots where x0 itself is nonzero (f_b = x0[pc_b], sigma = product of the
+      // d_b used so far), which leaves x a nonzero multiple of the exact
+      // reduction.  No modular inverse is needed.
+      uint32_t B[kMaxDepth];
+#pragma unroll
+      for (int t = 0; t < kMaxDepth; ++t) B[t] = 0;
+      int nb = 0;
+      int rowof = -1;              // lane c: the basis row whose pivot column is c
 #pragma unroll
       for (int q = 0; q < MW; ++q) {
         u64 bits = T[q];
         while (bits && !indep) {
           const int i = q * 64 + __builtin_ctzll(bits);
           bits &= bits - 1;
-          uint32_t x = col >= 0 ? tomod(net.Sint[(int64_t)i * net.n + col]) : 0u;
-          for (int b = 0; b < nb; ++b) {
-            const uint32_t f = __shfl(x, __shfl(pcreg, b));
-            if (f) x = submod(x, mulmod(f, basis[b * 64 + lane]));
+          int32_t c = 0;
+          if (dense) {
+            c = net.Sint[(int64_t)i * net.n + col];
+          } else {
+#pragma unroll
+            for (int e = 0; e < kMaxEnt; ++e)
+              if ((int)(ent[e] >> 16) == i) c = (int32_t)(int16_t)(ent[e] & 0xFFFFu);
+          }
+          const uint32_t x0 = tomod(c);
+          uint32_t x = x0, sigma = 1;
+          u64 hits = __ballot(x0 != 0 && rowof >= 0);
+          while (hits) {
+            const int pc = __ffsll((long long)hits) - 1;
+            hits &= hits - 1;
+            const int bidx = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_readlane(rowof, pc));
+            const uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)x0, pc);
+            const uint32_t rb = B[bidx];
+            const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)rb, pc);
+            x = submod(mulmod(d, x), mulmod(mulmod(sigma, f), rb));
+            sigma = mulmod(sigma, d);
           }
           const u64 nz = __ballot(x != 0);
           if (nz) {
             const int pc = __ffsll((long long)nz) - 1;
-            const uint32_t inv = powmod(__shfl(x, pc), kPrime - 2);
-            basis[nb * 64 + lane] = mulmod(x, inv);
-            if (lane == nb) pcreg = pc;
+            const uint32_t dn = (uint32_t)__builtin_amdgcn_readlane((int)x, pc);
+            for (int bb = 0; bb < nb; ++bb) {
+              const uint32_t rb = B[bb];
+              const uint32_t cb = (uint32_t)__builtin_amdgcn_readlane((int)rb, pc);
+              if (cb) B[bb] = submod(mulmod(dn, rb), mulmod(cb, x));
+            }
+            B[nb] = x;
+            if (lane == pc) rowof = nb;
             nb++;
-            if (nb == kq) indep = true;
+            if (nb == ncore) indep = true;
           }
         }
       }
     }
-    if (indep) {
-      if (lane == 0) {
-        atomicAdd(&L.counters[kIndep], 1ull);
-        if (keep_indep) {
-          const u64 idx = atomicAdd(&L.counters[kSurv], 1ull);
-          if ((int64_t)idx < L.ucap) L.surv[idx] = ref;
-          else atomicOr(&L.counters[kFlags], (u64)kFlagQueueOverflow);
-        } else {
-          atomicOr(&L.counters[kFlags], (u64)kFlagDepthCapped);
-        }
-      }
-    } else if (lane == 0) {
-      const u64 idx = atomicAdd(&L.counters[kExactQ], 1ull);
-      if ((int64_t)idx < L.ucap) L.exactq[idx] = ref;
-      else atomicOr(&L.counters[kFlags], (u64)kFlagQueueOverflow);
-    }
+    if (L.debug_prime) indep = false;
+    n_indep += (indep && lane == 0) ? 1 : 0;
+    n_capped += (indep && !keep_indep && lane == 0) ? 1 : 0;
+    wbuf_push(bsurv, indep && keep_indep && lane == 0, ref, L.surv, &L.counters[cslot(kSurv)], L.ucap,
+              &L.counters[cslot(kFlags)]);
+    wbuf_push(bexact, !indep && lane == 0, ref, L.exactq, &L.counters[cslot(kExactQ)], L.ucap,
+              &L.counters[cslot(kFlags)]);
   }
+  wbuf_flush(bsurv, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
+  wbuf_flush(bexact, L.exactq, &L.counters[cslot(kExactQ)], L.ucap, &L.counters[cslot(kFlags)]);
+  u64 v[3] = {n_indep, n_pruned, n_capped};
+  const int slots[3] = {kIndep, kPruned, kCapped};
+  block_counts<3>(v, L.counters, slots);
 }
 
 // ------------------------------------------------------------------------- exact
@@ -397,7 +570,7 @@ __global__ __launch_bounds__(256) void rank_kernel(DevNet net, DevLevel L, int p
 template <int W, int MW>
 __global__ __launch_bounds__(64) void exact_kernel(DevNet net, DevLevel L) {
   const int lane = lane_id();
-  const int64_t nitems = min((int64_t)L.counters[kExactQ], L.ucap);
+  const int64_t nitems = min((int64_t)L.counters[cslot(kExactQ)], L.ucap);
   const bool keep_indep = L.level + 1 < L.depth_cap;
   i128 *M = L.xscratch + (size_t)blockIdx.x * (size_t)net.mi * 64;
 
@@ -465,18 +638,18 @@ __global__ __launch_bounds__(64) void exact_kernel(DevNet net, DevLevel L) {
       rank++;
     }
     if (__ballot(ovf)) {
-      if (lane == 0) atomicOr(&L.counters[kFlags], (u64)kFlagIntOverflow);
+      if (lane == 0) atomicOr(&L.counters[cslot(kFlags)], (u64)kFlagIntOverflow);
       continue;
     }
     if (rank == kq) {                      // the modular test was fooled: independent
       if (lane == 0) {
-        atomicAdd(&L.counters[kIndep], 1ull);
+        atomicAdd(&L.counters[cslot(kIndep)], 1ull);
         if (keep_indep) {
-          const u64 idx = atomicAdd(&L.counters[kSurv], 1ull);
+          const u64 idx = atomicAdd(&L.counters[cslot(kSurv)], 1ull);
           if ((int64_t)idx < L.ucap) L.surv[idx] = ref;
-          else atomicOr(&L.counters[kFlags], (u64)kFlagQueueOverflow);
+          else atomicOr(&L.counters[cslot(kFlags)], (u64)kFlagQueueOverflow);
         } else {
-          atomicOr(&L.counters[kFlags], (u64)kFlagDepthCapped);
+          atomicAdd(&L.counters[cslot(kCapped)], 1ull);
         }
       }
       continue;
@@ -521,7 +694,7 @@ __global__ __launch_bounds__(64) void exact_kernel(DevNet net, DevLevel L) {
       ovf = __ballot(ovf) != 0;
     }
     if (ovf) {
-      if (lane == 0) atomicOr(&L.counters[kFlags], (u64)kFlagIntOverflow);
+      if (lane == 0) atomicOr(&L.counters[cslot(kFlags)], (u64)kFlagIntOverflow);
       continue;
     }
 
@@ -538,87 +711,189 @@ __global__ __launch_bounds__(64) void exact_kernel(DevNet net, DevLevel L) {
     if (prod <= 0) continue;
     const i128 lim = (i128)1 << 63;
     if (__ballot(v >= lim || v < -lim) != 0) {
-      if (lane == 0) atomicOr(&L.counters[kFlags], (u64)kFlagIntOverflow);
+      if (lane == 0) atomicOr(&L.counters[cslot(kFlags)], (u64)kFlagIntOverflow);
       continue;
     }
     u64 slot = 0;
-    if (lane == 0) slot = atomicAdd(&L.counters[kFound], 1ull);
+    if (lane == 0) slot = atomicAdd(&L.counters[cslot(kFound)], 1ull);
     slot = __shfl(slot, 0);
     if ((int64_t)slot >= L.ecap) {
-      if (lane == 0) atomicOr(&L.counters[kFlags], (u64)kFlagFoundOverflow);
+      if (lane == 0) atomicOr(&L.counters[cslot(kFlags)], (u64)kFlagFoundOverflow);
       continue;
     }
 #pragma unroll
     for (int w = 0; w < W; ++w)
       if (lane == w) L.fkeys[(int64_t)w * L.ecap + slot] = Q[w];
     if (mine) L.fflux[(int64_t)slot * kMaxDepth + lane] = (int64_t)v;
-    if (lane == 0) atomicAdd(&L.counters[kEmitted], 1ull);
+    if (lane == 0) atomicAdd(&L.counters[cslot(kEmitted)], 1ull);
   }
 }
 
 // ------------------------------------------------------------- truncation select
+
+// Radix selection of the frontier cap's smallest keys, one key byte per pass from
+// the most significant.  sel[i] is 2 while survivor i is undecided, then 1
+// (selected) or 0 (rejected).  skey[i] caches the key word the current byte
+// lies in; it is refilled when a pass enters a new word.
 template <int W>
-DEVI uint32_t key_byte(const DevLevel &L, u64 ref, int byte) {
+DEVI u64 key_word(const DevLevel &L, u64 ref, int w) {
   const u64 p = ref >> 12;
   const int r = (int)((ref >> 1) & 0x7FF);
-  const int w = byte >> 3;
-  u64 kw = L.keys[(int64_t)w * L.fcap + p] | ((r >> 6) == w ? (1ull << (r & 63)) : 0ull);
-  return (uint32_t)((kw >> ((byte & 7) * 8)) & 0xFF);
+  return L.keys[(int64_t)w * L.fcap + p] | ((r >> 6) == w ? (1ull << (r & 63)) : 0ull);
 }
 
+// Histogram of the undecided members' digits for pass `pass` (state and histogram
+// are double-buffered by pass parity).  Digits are highly skewed (the top bytes
+// of nearly all keys agree), so each wave groups its lanes by digit and adds one
+// count per distinct digit.
 template <int W>
-__global__ __launch_bounds__(256) void select_hist_kernel(DevLevel L, int byte, int first, int64_t nb) {
+__global__ __launch_bounds__(256) void select_hist_kernel(DevLevel L, int byte, int refill, int pass) {
   __shared__ uint32_t h[256];
+  const SelState *st = L.selst + (pass & 1);
+  if (st->done) return;
+  uint32_t *hist = L.hist + 256 * (pass & 1);
+  const int64_t n = min((int64_t)L.counters[cslot(kSurv)], L.ucap);
   h[threadIdx.x] = 0;
   __syncthreads();
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t idx = first ? i : (int64_t)L.blist[i];
-    atomicAdd(&h[key_byte<W>(L, L.surv[idx], byte)], 1u);
-  }
-  __syncthreads();
-  if (h[threadIdx.x]) atomicAdd(&L.hist[threadIdx.x], h[threadIdx.x]);
-}
-
-template <int W>
-__global__ __launch_bounds__(256) void select_split_kernel(DevLevel L, int byte, int first, int64_t nb,
-                                                           uint32_t digit, int all_sel) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nb; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t idx = first ? i : (int64_t)L.blist[i];
-    const uint32_t d = key_byte<W>(L, L.surv[idx], byte);
-    if (d < digit || (d == digit && all_sel)) {
-      L.sel[idx] = 1;
-    } else if (d == digit) {
-      const u64 k = atomicAdd(&L.counters[kBoundary], 1ull);
-      L.blist2[k] = (uint32_t)idx;
-    }
-  }
-}
-
-// ------------------------------------------------------------------ materialize
-template <int W>
-__global__ __launch_bounds__(256) void materialize_kernel(DevNet net, DevLevel L, int use_sel) {
-  const int64_t n = min((int64_t)L.counters[kSurv], L.ucap);
   const int lane = lane_id();
+  const int shift = (byte & 7) * 8;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
   for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
-    const int64_t idx = base + lane;
-    const bool act = idx < n && (!use_sel || L.sel[idx] == 1);
-    u64 ref = act ? L.surv[idx] : 0ull;
-    const u64 mask = __ballot(act);
-    if (mask == 0) continue;
-    const int leader = __ffsll((long long)mask) - 1;
-    u64 dst = 0;
-    if (lane == leader) dst = atomicAdd(&L.counters[kNext], (u64)__popcll(mask));
-    dst = __shfl(dst, leader) + (u64)__popcll(mask & lanes_below(lane));
+    const int64_t i = base + lane;
+    const bool act = i < n && L.sel[i] == 2;
+    if (__ballot(act) == 0) continue;
+    uint32_t d = 0;
     if (act) {
-      const u64 p = ref >> 12;
-      const int r = (int)((ref >> 1) & 0x7FF);
+      u64 kw;
+      if (refill) {
+        kw = key_word<W>(L, L.surv[i], byte >> 3);
+        L.skey[i] = kw;
+      } else {
+        kw = L.skey[i];
+      }
+      d = (uint32_t)((kw >> shift) & 0xFF);
+    }
+    u64 pending = __ballot(act);
+    while (pending) {
+      const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)d, __ffsll((long long)pending) - 1);
+      const u64 m = __ballot(act && d == v) & pending;
+      if (lane == __ffsll((long long)m) - 1) atomicAdd(&h[v], (uint32_t)__popcll(m));
+      pending &= ~m;
+    }
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// Every block derives the pass's decision from the finished histogram: the
+// boundary digit v (undecided members below it are selected, above it
+// rejected), whether every member with digit v fits, or whether the pass decides
+// nothing.  Block 0 writes the next pass's state and clears its histogram.
+template <int W>
+__global__ __launch_bounds__(256) void select_split_kernel(DevLevel L, int byte, int pass) {
+  __shared__ uint32_t dec[3];
+  __shared__ int64_t rem;
+  const SelState *st = L.selst + (pass & 1);
+  SelState *nx = L.selst + ((pass + 1) & 1);
+  const uint32_t *hist = L.hist + 256 * (pass & 1);
+  const bool lead = blockIdx.x == 0;
+  if (lead) L.hist[256 * ((pass + 1) & 1) + threadIdx.x] = 0;
+  if (st->done) {
+    if (lead && threadIdx.x == 0) *nx = *st;
+    return;
+  }
+  if (threadIdx.x == 0) {
+    int64_t cum = 0;
+    int v = 0;
+    for (v = 0; v < 255; ++v) {
+      if (cum + (int64_t)hist[v] >= st->needed) break;
+      cum += hist[v];
+    }
+    const int64_t hv = hist[v];
+    const int64_t remaining = st->needed - cum;
+    const uint32_t all_sel = hv == remaining ? 1u : 0u;
+    dec[0] = (uint32_t)v;
+    dec[1] = all_sel;
+    dec[2] = (!all_sel && hv == st->nb) ? 1u : 0u;
+    rem = remaining;
+    if (lead) {
+      SelState t = *st;
+      if (!dec[2]) {
+        t.needed = remaining;
+        t.nb = hv;
+        t.done = all_sel;
+      }
+      *nx = t;
+    }
+  }
+  __syncthreads();
+  if (dec[2]) return;                       // one digit only: nothing decided here
+  const uint32_t digit = dec[0];
+  const int all_sel = (int)dec[1];
+  const int shift = (byte & 7) * 8;
+  const int64_t n = min((int64_t)L.counters[cslot(kSurv)], L.ucap);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    if (L.sel[i] != 2) continue;
+    const uint32_t d = (uint32_t)((L.skey[i] >> shift) & 0xFF);
+    if (d < digit || (d == digit && all_sel)) L.sel[i] = 1;
+    else if (d > digit) L.sel[i] = 0;
+  }
+}
+
+// Writes the next frontier.  Without a cap the survivor order is kept (position =
+// survivor index).  With a cap the selected members are compacted with one global
+// atomic per block and per 1024 survivors.
+template <int W>
+__global__ __launch_bounds__(256) void materialize_kernel(DevNet net, DevLevel L, int use_sel) {
+  __shared__ uint32_t wcount[4][4];
+  __shared__ u64 bbase;
+  const int64_t n = min((int64_t)L.counters[cslot(kSurv)], L.ucap);
+  const int lane = lane_id();
+  const int wib = threadIdx.x >> 6;
+  for (int64_t base = (int64_t)blockIdx.x * 1024; base < n; base += (int64_t)gridDim.x * 1024) {
+    bool act[4];
+    u64 ref[4], dst[4];
+    u64 mask[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t idx = base + t * 256 + threadIdx.x;
+      act[t] = idx < n && (!use_sel || L.sel[idx] == 1);
+      ref[t] = act[t] ? L.surv[idx] : 0ull;
+      dst[t] = (u64)idx;
+      mask[t] = __ballot(act[t]);
+    }
+    if (use_sel) {
+      if (lane == 0)
+        for (int t = 0; t < 4; ++t) wcount[t][wib] = (uint32_t)__popcll(mask[t]);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t tot = 0;
+        for (int t = 0; t < 4; ++t)
+          for (int w = 0; w < 4; ++w) tot += wcount[t][w];
+        bbase = tot ? atomicAdd(&L.counters[cslot(kNext)], (u64)tot) : 0ull;
+      }
+      __syncthreads();
+      u64 off = bbase;
+      for (int t = 0; t < 4; ++t) {
+        for (int w = 0; w < 4; ++w) {
+          if (w == wib) dst[t] = off + (u64)__popcll(mask[t] & lanes_below(lane));
+          off += wcount[t][w];
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (!act[t]) continue;
+      const u64 p = ref[t] >> 12;
+      const int r = (int)((ref[t] >> 1) & 0x7FF);
 #pragma unroll
       for (int w = 0; w < W; ++w)
-        L.nkeys[(int64_t)w * L.fcap + dst] =
+        L.nkeys[(int64_t)w * L.fcap + dst[t]] =
             L.keys[(int64_t)w * L.fcap + p] | ((r >> 6) == w ? (1ull << (r & 63)) : 0ull);
-      L.nhash[dst] = L.hash[p] ^ net.zob[r];
+      L.nhash[dst[t]] = L.hash[p] ^ net.zob[r];
     }
   }
 }
@@ -682,7 +957,7 @@ template <int W, int MW>
 static void do_rank(const DevNet &net, const DevLevel &L, int prune, hipStream_t s) {
   const int kq_max = L.level + 1;
   const int wpb = 4;
-  const size_t lds = (size_t)wpb * kq_max * 64 * sizeof(uint32_t);
+  const size_t lds = 0;
   hipLaunchKernelGGL((rank_kernel<W, MW>), dim3((unsigned)(num_cus() * 8)), dim3(64 * wpb), lds, s, net, L,
                      prune, kq_max);
 }
@@ -710,24 +985,22 @@ hipError_t launch_materialize(const DevNet &net, const DevLevel &L, int use_sel,
 }
 
 template <int W>
-static void do_hist(const DevLevel &L, int byte, int first, int64_t nb, hipStream_t s) {
-  hipLaunchKernelGGL((select_hist_kernel<W>), dim3((unsigned)(num_cus() * 4)), dim3(256), 0, s, L, byte, first, nb);
+static void do_hist(const DevLevel &L, int byte, int refill, int pass, hipStream_t s) {
+  hipLaunchKernelGGL((select_hist_kernel<W>), dim3((unsigned)(num_cus() * 4)), dim3(256), 0, s, L, byte, refill,
+                     pass);
 }
-hipError_t launch_select_hist(const DevNet &net, const DevLevel &L, int byte, int first, int64_t nb,
+hipError_t launch_select_hist(const DevNet &net, const DevLevel &L, int byte, int refill, int pass,
                               hipStream_t s) {
-  EFM_DISPATCH_W(net.Wt, do_hist, L, byte, first, nb, s);
+  EFM_DISPATCH_W(net.Wt, do_hist, L, byte, refill, pass, s);
   return hipGetLastError();
 }
 
 template <int W>
-static void do_split(const DevLevel &L, int byte, int first, int64_t nb, uint32_t digit, int all_sel,
-                     hipStream_t s) {
-  hipLaunchKernelGGL((select_split_kernel<W>), dim3((unsigned)(num_cus() * 4)), dim3(256), 0, s, L, byte, first,
-                     nb, digit, all_sel);
+static void do_split(const DevLevel &L, int byte, int pass, hipStream_t s) {
+  hipLaunchKernelGGL((select_split_kernel<W>), dim3((unsigned)(num_cus() * 4)), dim3(256), 0, s, L, byte, pass);
 }
-hipError_t launch_select_split(const DevNet &net, const DevLevel &L, int byte, int first, int64_t nb,
-                               uint32_t digit, int all_sel, hipStream_t s) {
-  EFM_DISPATCH_W(net.Wt, do_split, L, byte, first, nb, digit, all_sel, s);
+hipError_t launch_select_split(const DevNet &net, const DevLevel &L, int byte, int pass, hipStream_t s) {
+  EFM_DISPATCH_W(net.Wt, do_split, L, byte, pass, s);
   return hipGetLastError();
 }
 

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libefm.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW = 0, -1, -2, -3, -4
 COMPLETE, DEPTH_CAPPED, FRONTIER_TRUNCATED = 0, 1, 2
-OPT_NO_PRUNE, OPT_EXACT_RANK, OPT_TIME_KERNELS = 1, 2, 4
+OPT_NO_PRUNE, OPT_EXACT_RANK, OPT_TIME_KERNELS, OPT_NO_GF2 = 1, 2, 4, 8
 MAX_DEPTH = 64
 
 EXPORTS = ["efm_network_create", "efm_network_destroy", "efm_workspace_query", "efm_enumerate",

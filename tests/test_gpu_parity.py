@@ -106,6 +106,17 @@ def test_exact_rank_option_changes_nothing():
             _same(net, x, flags=efm.OPT_EXACT_RANK)
 
 
+def test_modp_only_option_changes_nothing():
+    for seed in (1, 3):
+        net = netgen.tiny(seed)
+        for x in net.targets:
+            _same(net, x, flags=efm.OPT_NO_GF2)
+    net = netgen.central(1)
+    _same(net, net.targets[3], depth_cap=12, frontier_cap=4000, flags=efm.OPT_NO_GF2)
+    net = netgen.genome(0)
+    _same(net, net.targets[0], depth_cap=10, frontier_cap=1000, flags=efm.OPT_NO_GF2)
+
+
 def test_no_prune_option_changes_nothing():
     net = netgen.tiny(3)
     for x in net.targets:
