@@ -223,7 +223,7 @@ struct Layout {
   int64_t ucap, fcap, ecap, tcap;
   int xwaves;
   size_t off_counters, off_hist, off_selst, off_root, off_sx, off_fa_keys, off_fa_hash, off_fb_keys, off_fb_hash,
-      off_table, off_surv, off_rankq, off_exactq, off_sel, off_skey, off_fkeys, off_fflux,
+      off_table, off_surv, off_rankq, off_parq, off_parmask, off_exactq, off_sel, off_skey, off_fkeys, off_fflux,
       off_xs, total;
 };
 
@@ -257,6 +257,8 @@ Layout make_layout(const efm_network *N, const efm_enum_opts *o) {
   L.off_table = take((size_t)L.tcap * 8);
   L.off_surv = take((size_t)L.ucap * 8);
   L.off_rankq = take((size_t)L.ucap * 8);
+  L.off_parq = take((size_t)L.ucap * 8);
+  L.off_parmask = take((size_t)L.ucap * Wt * 8);
   L.off_exactq = take((size_t)L.ucap * 8);
   L.off_sel = take((size_t)L.ucap);
   L.off_skey = take((size_t)L.ucap * 8);
@@ -337,6 +339,8 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
   L.table = (u64 *)(ws + Lo.off_table);
   L.surv = (u64 *)(ws + Lo.off_surv);
   L.rankq = (u64 *)(ws + Lo.off_rankq);
+  L.parq = (u64 *)(ws + Lo.off_parq);
+  L.parmask = (u64 *)(ws + Lo.off_parmask);
   L.exactq = (u64 *)(ws + Lo.off_exactq);
   L.ucap = Lo.ucap;
   L.fcap = Lo.fcap;
@@ -388,7 +392,8 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
         if (timing) HIPCHK(hipEventRecord(ev[0], s));
         HIPCHK(efm::launch_expand(N->dn, L, s));
         if (timing) HIPCHK(hipEventRecord(ev[1], s));
-        HIPCHK(efm::launch_rank(N->dn, L, (o.flags & EFM_OPT_NO_PRUNE) ? 0 : 1, s));
+        HIPCHK(efm::launch_rank_parent(N->dn, L, (o.flags & EFM_OPT_NO_PRUNE) ? 0 : 1, s));
+        HIPCHK(efm::launch_rank(N->dn, L, 0, s));
         if (timing) HIPCHK(hipEventRecord(ev[2], s));
         HIPCHK(efm::launch_exact(N->dn, L, s));
         if (timing) HIPCHK(hipEventRecord(ev[3], s));
@@ -452,7 +457,7 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
     st.parents = nparents;
     st.children = (int64_t)hc[efm::kChildren];
     st.unique = (int64_t)hc[efm::kUnique];
-    st.row_closed = (int64_t)hc[efm::kRankQ];
+    st.row_closed = (int64_t)hc[efm::kRowClosed];
     st.pruned = (int64_t)hc[efm::kPruned];
     st.independent = (int64_t)hc[efm::kIndep];
     st.emitted = (int64_t)hc[efm::kEmitted];

@@ -31,6 +31,8 @@ enum Counter {
   kFlags,          // EFM_* flags and overflow bits below
   kBoundary,       // radix-select boundary list length
   kCapped,         // independent children dropped by the depth cap
+  kParQ,           // parents queued with their row-closed children
+  kRowClosed,      // distinct row-closed children
   kNumCounters
 };
 // Counters sit 256 bytes apart so that atomics on different counters never share
@@ -92,7 +94,9 @@ struct DevLevel {
   u64 tmask;              // slots used by this level - 1 (a power of two minus one)
   int tag;                // 1..127, distinct for every expand launch since the last clear
   u64 *surv;              // [ucap] refs of independent children
-  u64 *rankq;             // [ucap] refs of row-closed children
+  u64 *rankq;             // [ucap] refs of row-closed children left undecided per parent
+  u64 *parq;              // [ucap] parents with distinct row-closed children
+  u64 *parmask;           // [ucap][Wt] those children, as a reaction mask
   u64 *exactq;            // [ucap] refs needing exact arithmetic
   int64_t ucap;
   // next frontier
@@ -121,6 +125,7 @@ struct DevLevel {
 // kernel launchers (efm_kernels.hip)
 hipError_t launch_expand(const DevNet &net, const DevLevel &L, hipStream_t s);
 hipError_t launch_rank(const DevNet &net, const DevLevel &L, int prune, hipStream_t s);
+hipError_t launch_rank_parent(const DevNet &net, const DevLevel &L, int prune, hipStream_t s);
 hipError_t launch_exact(const DevNet &net, const DevLevel &L, hipStream_t s);
 hipError_t launch_materialize(const DevNet &net, const DevLevel &L, int use_sel, hipStream_t s);
 hipError_t launch_select_hist(const DevNet &net, const DevLevel &L, int byte, int refill, int pass,

@@ -113,6 +113,22 @@ DEVI u64 wave_or(u64 v) {
   return v;
 }
 
+// 64x64 bit-matrix transpose across the wave: on entry lane j holds row j, on
+// exit lane b holds bit b of every lane's entry row (bit j = entry lane j, bit b).
+DEVI u64 wave_transpose64(u64 a) {
+  const int lane = lane_id();
+  const u64 masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
+                        0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
+#pragma unroll
+  for (int st = 0; st < 6; ++st) {
+    const int j = 32 >> st;
+    const u64 m = masks[st];
+    const u64 other = __shfl_xor(a, j);
+    a = (lane & j) ? ((a & ~m) | ((other & ~m) >> j)) : ((a & m) | ((other & m) << j));
+  }
+  return a;
+}
+
 DEVI i128 shfl_i128(i128 v, int src) {
   unsigned __int128 u = (unsigned __int128)v;
   u64 lo = (u64)u, hi = (u64)(u >> 64);
@@ -306,10 +322,13 @@ __global__ __launch_bounds__(256) void expand_kernel(DevNet net, DevLevel L) {
   }
 
   // children: uniform trip count per wave so the ballots stay converged
-  __shared__ u64 stage[2][4][kWaveBuf];
+  __shared__ u64 stage[4][kWaveBuf];
   const int wib = threadIdx.x >> 6;
-  WaveBuf bsurv{stage[0][wib], 0}, brank{stage[1][wib], 0};
-  u64 n_unique = 0, n_indep = 0, n_capped = 0;
+  WaveBuf bsurv{stage[wib], 0};
+  u64 n_unique = 0, n_indep = 0, n_capped = 0, n_rc = 0;
+  u64 rcm[W];                  // this parent's distinct row-closed children
+#pragma unroll
+  for (int w = 0; w < W; ++w) rcm[w] = 0;
   const int maxc = wave_max_int(ncand);
   for (int it = 0; it < maxc; ++it) {
     const bool act = it < ncand;
@@ -335,16 +354,195 @@ __global__ __launch_bounds__(256) void expand_kernel(DevNet net, DevLevel L) {
     const u64 ref = ((u64)p << 12) | ((u64)r << 1) | (rc ? 1ull : 0ull);
     wbuf_push(bsurv, uniq && !rc && keep_indep, ref, L.surv, &L.counters[cslot(kSurv)], L.ucap,
               &L.counters[cslot(kFlags)]);
-    wbuf_push(brank, uniq && rc, ref, L.rankq, &L.counters[cslot(kRankQ)], L.ucap, &L.counters[cslot(kFlags)]);
+    if (uniq && rc) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) rcm[w] |= (r >> 6) == w ? (1ull << (r & 63)) : 0ull;
+    }
+    n_rc += (uniq && rc) ? 1 : 0;
     n_unique += uniq ? 1 : 0;
     n_indep += (uniq && !rc) ? 1 : 0;
     n_capped += (uniq && !rc && !keep_indep) ? 1 : 0;
   }
   wbuf_flush(bsurv, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
-  wbuf_flush(brank, L.rankq, &L.counters[cslot(kRankQ)], L.ucap, &L.counters[cslot(kFlags)]);
-  u64 v[4] = {(u64)ncand, n_unique, n_indep, n_capped};
-  const int slots[4] = {kChildren, kUnique, kIndep, kCapped};
-  block_counts<4>(v, L.counters, slots);
+  {
+    // one rank-queue entry per parent that has row-closed children
+    bool any = false;
+#pragma unroll
+    for (int w = 0; w < W; ++w) any = any || rcm[w] != 0;
+    const u64 m = __ballot(any);
+    if (m) {
+      const int leader = __ffsll((long long)m) - 1;
+      u64 b0 = 0;
+      if (lane_id() == leader) b0 = atomicAdd(&L.counters[cslot(kParQ)], (u64)__popcll(m));
+      b0 = __shfl(b0, leader);
+      if (any) {
+        const u64 idx = b0 + (u64)__popcll(m & lanes_below(lane_id()));
+        if ((int64_t)idx < L.ucap) {
+          L.parq[idx] = (u64)p;
+#pragma unroll
+          for (int w = 0; w < W; ++w) L.parmask[(int64_t)idx * W + w] = rcm[w];
+        } else {
+          atomicOr(&L.counters[cslot(kFlags)], (u64)kFlagQueueOverflow);
+        }
+      }
+    }
+  }
+  u64 v[5] = {(u64)ncand, n_unique, n_indep, n_capped, n_rc};
+  const int slots[5] = {kChildren, kUnique, kIndep, kCapped, kRowClosed};
+  block_counts<5>(v, L.counters, slots);
+}
+
+// ------------------------------------------------------------------- rank (parent)
+// One wave per parent P with its distinct row-closed children r_1..r_m.  Every
+// child's rows lie inside P's rows.  Lane j holds column j of P | {r_1..r_m}.
+// The rows are bit masks over those columns (odd coefficients); XOR elimination
+// over P's columns only, applied to whole rows, leaves each child's column
+// reduced against P modulo 2, so a child is certified independent exactly when
+// its reduced column has a 1 in a row P did not use as a pivot.  Independence
+// modulo 2 implies independence over the rationals.  Children not certified
+// (or pruned by the found set) go on to the per-child test.
+template <int W, int MW>
+__global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L, int prune) {
+  __shared__ u64 stage[2][4][kWaveBuf];
+  const int wib = threadIdx.x >> 6;
+  const int lane = lane_id();
+  const int wpb = blockDim.x >> 6;
+  const int64_t nitems = min((int64_t)L.counters[cslot(kParQ)], L.ucap);
+  const bool keep_indep = L.level + 1 < L.depth_cap;
+  const int64_t nf = min((int64_t)L.nfound_prev, L.ecap);
+  WaveBuf bsurv{stage[0][wib], 0}, bslow{stage[1][wib], 0};
+  u64 n_indep = 0, n_pruned = 0, n_capped = 0;
+
+  for (int64_t item = (int64_t)blockIdx.x * wpb + wib; item < nitems; item += (int64_t)gridDim.x * wpb) {
+    const u64 p = L.parq[item];
+    u64 P[W], M[W], A[W];
+    int kall = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      P[w] = L.keys[(int64_t)w * L.fcap + p];
+      M[w] = L.parmask[item * W + w];
+      A[w] = P[w] | M[w];
+      kall += __popcll(A[w]);
+    }
+    // found-set prune, child by child
+    if (prune && nf > 0 && nf <= kPruneMax) {
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        u64 bits = M[w];
+        while (bits) {
+          const int r = w * 64 + __builtin_ctzll(bits);
+          bits &= bits - 1;
+          bool hit = false;
+          for (int64_t f0 = 0; f0 < nf && !hit; f0 += 64) {
+            const int64_t f = f0 + lane;
+            bool sub = f < nf;
+            if (sub) {
+#pragma unroll
+              for (int ww = 0; ww < W; ++ww) {
+                const u64 Qw = P[ww] | ((r >> 6) == ww ? (1ull << (r & 63)) : 0ull);
+                sub = sub && ((L.fkeys[(int64_t)ww * L.ecap + f] & ~Qw) == 0);
+              }
+            }
+            hit = __ballot(sub) != 0;
+          }
+          if (hit) {
+            n_pruned += lane == 0 ? 1 : 0;
+            M[w] &= ~(1ull << (r & 63));
+          }
+        }
+      }
+    }
+    kall = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      A[w] = P[w] | M[w];                        // pruned children are gone from M
+      kall += __popcll(A[w]);
+    }
+    bool full = kall <= 64 && !L.debug_prime && !L.no_gf2;
+    u64 rowm[MW];
+    bool used[MW];
+    int col = -1;
+    bool child = false;
+    if (full) {
+      col = lane < kall ? select_bit<W>(A, lane) : -1;
+#pragma unroll
+      for (int w = 0; w < W; ++w)
+        if (col >= 0 && (col >> 6) == w) child = (M[w] >> (col & 63)) & 1ull;
+      u64 om[MW], tm[MW];
+#pragma unroll
+      for (int q = 0; q < MW; ++q) {
+        om[q] = col >= 0 ? net.rxn_oddM[(int64_t)col * MW + q] : 0ull;
+        tm[q] = (col >= 0 && !child) ? net.rxn_touchM[(int64_t)col * MW + q] : 0ull;
+      }
+#pragma unroll
+      for (int q = 0; q < MW; ++q) {
+        // rows P does not touch are dropped (used) so they never serve as pivots
+        const u64 T = wave_or(tm[q]);
+        rowm[q] = wave_transpose64(om[q]);
+        used[q] = !((T >> lane) & 1ull);
+      }
+      u64 cols = __ballot(col >= 0 && !child);
+      while (cols) {
+        const int c = __ffsll((long long)cols) - 1;
+        cols &= cols - 1;
+        int pq = -1, pl = -1;
+#pragma unroll
+        for (int q = 0; q < MW; ++q) {
+          if (pq < 0) {
+            const u64 cand = __ballot(!used[q] && ((rowm[q] >> c) & 1ull));
+            if (cand) { pq = q; pl = __ffsll((long long)cand) - 1; }
+          }
+        }
+        if (pq < 0) { full = false; break; }
+        u64 prow = 0;
+#pragma unroll
+        for (int q = 0; q < MW; ++q) {
+          if (q == pq) {
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)rowm[q], pl);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(rowm[q] >> 32), pl);
+            prow = ((u64)hi << 32) | lo;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < MW; ++q) {
+          const bool me = (q == pq) && (lane == pl);
+          if (!me && ((rowm[q] >> c) & 1ull)) rowm[q] ^= prow;
+          if (me) used[q] = true;
+        }
+      }
+    }
+    // children, in reaction order: certified ones are independent
+    u64 ccols = __ballot(child);
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+      u64 bits = M[w];
+      while (bits) {
+        const int r = w * 64 + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        bool cert = false;
+        if (full) {
+          const int c = __ffsll((long long)ccols) - 1;   // children's columns come in reaction order
+          ccols &= ccols - 1;
+          bool any = false;
+#pragma unroll
+          for (int q = 0; q < MW; ++q) any = any || (!used[q] && ((rowm[q] >> c) & 1ull));
+          cert = __ballot(any) != 0;
+        }
+        const u64 ref = (p << 12) | ((u64)r << 1) | 1ull;
+        n_indep += (cert && lane == 0) ? 1 : 0;
+        n_capped += (cert && !keep_indep && lane == 0) ? 1 : 0;
+        wbuf_push(bsurv, cert && keep_indep && lane == 0, ref, L.surv, &L.counters[cslot(kSurv)], L.ucap,
+                  &L.counters[cslot(kFlags)]);
+        wbuf_push(bslow, !cert && lane == 0, ref, L.rankq, &L.counters[cslot(kRankQ)], L.ucap,
+                  &L.counters[cslot(kFlags)]);
+      }
+    }
+  }
+  wbuf_flush(bsurv, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
+  wbuf_flush(bslow, L.rankq, &L.counters[cslot(kRankQ)], L.ucap, &L.counters[cslot(kFlags)]);
+  u64 v[3] = {n_indep, n_pruned, n_capped};
+  const int slots[3] = {kIndep, kPruned, kCapped};
+  block_counts<3>(v, L.counters, slots);
 }
 
 // -------------------------------------------------------------------------- rank
@@ -443,15 +641,8 @@ __global__ __launch_bounds__(256) void rank_kernel(DevNet net, DevLevel L, int p
 #pragma unroll
       for (int q = 0; q < MW; ++q) {
         om[q] = alive ? net.rxn_oddM[(int64_t)col * MW + q] : 0ull;
-        rowm[q] = 0;
-        used[q] = false;
-        u64 bits = T[q];
-        while (bits) {
-          const int b = __builtin_ctzll(bits);
-          bits &= bits - 1;
-          const u64 m = __ballot((om[q] >> b) & 1ull);
-          if (lane == b) rowm[q] = m;
-        }
+        rowm[q] = wave_transpose64(om[q]);
+        used[q] = !((T[q] >> lane) & 1ull);
       }
       u64 cols = __ballot(alive);
       bool ok = true;
@@ -954,11 +1145,20 @@ hipError_t launch_expand(const DevNet &net, const DevLevel &L, hipStream_t s) {
 }
 
 template <int W, int MW>
+static void do_rank_parent(const DevNet &net, const DevLevel &L, int prune, hipStream_t s) {
+  hipLaunchKernelGGL((rank_parent_kernel<W, MW>), dim3((unsigned)(num_cus() * 16)), dim3(256), 0, s, net, L, prune);
+}
+hipError_t launch_rank_parent(const DevNet &net, const DevLevel &L, int prune, hipStream_t s) {
+  EFM_DISPATCH_WM(net.Wt, net.MWt, do_rank_parent, net, L, prune, s);
+  return hipGetLastError();
+}
+
+template <int W, int MW>
 static void do_rank(const DevNet &net, const DevLevel &L, int prune, hipStream_t s) {
   const int kq_max = L.level + 1;
   const int wpb = 4;
   const size_t lds = 0;
-  hipLaunchKernelGGL((rank_kernel<W, MW>), dim3((unsigned)(num_cus() * 8)), dim3(64 * wpb), lds, s, net, L,
+  hipLaunchKernelGGL((rank_kernel<W, MW>), dim3((unsigned)(num_cus() * 16)), dim3(64 * wpb), lds, s, net, L,
                      prune, kq_max);
 }
 hipError_t launch_rank(const DevNet &net, const DevLevel &L, int prune, hipStream_t s) {
