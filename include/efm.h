@@ -77,6 +77,8 @@ typedef struct {
                                     modulo a prime first (slower; result unchanged) */
 #define EFM_OPT_NO_GF2 8u        /* skip the modulo-2 independence certificate, so every undecided
                                     rank test runs modulo the prime (result unchanged) */
+#define EFM_OPT_AUTOTUNE 16u     /* batch only: time candidate tile shapes once at creation and keep
+                                    the fastest */
 #define EFM_OPT_TIME_KERNELS 4u  /* record HIP events around every kernel launch on the stream and
                                     report per-level kernel times in efm_level_stats */
 
@@ -137,6 +139,45 @@ efm_status efm_result_bitsets(const efm_result *res, uint64_t *dst, int64_t dst_
 /* dst: host, n_pathways * n_rxn int64, dense fluxes in the same order. */
 efm_status efm_result_fluxes(const efm_result *res, int64_t *dst, int64_t dst_len);
 efm_status efm_result_destroy(efm_result *res);
+
+/* ---------------------------------------------------------------- batches
+ * Many independent networks, each with one target, traversed in one persistent
+ * kernel launch: every workgroup pops a network from a device work queue and
+ * runs its whole level loop (the same method as efm_enumerate).  The launch is
+ * captured once in a HIP graph and replayed by efm_batch_run.  Per-network
+ * results equal those of efm_enumerate with the same options.
+ *
+ * efm_batch_create: nets[i] (created by efm_network_create, at most 256
+ *   reactions and 128 internal metabolites each) with targets[i] (an external
+ *   metabolite of nets[i]); opts supplies depth_cap, frontier_cap (per network and
+ *   level), unique_cap (distinct children per network and level, default 262144),
+ *   found_cap (pathways per network, default 4096) and flags (EFM_OPT_NO_PRUNE,
+ *   EFM_OPT_EXACT_RANK, EFM_OPT_NO_GF2, EFM_OPT_AUTOTUNE); opts->workspace and
+ *   opts->stream are not used.  The batch owns its device memory and a private
+ *   stream; the networks must outlive the call only.
+ *   Errors: EFM_EINVAL (null, empty, too large, bad target), EFM_EDEVICE.
+ * efm_batch_run: replays the graph on `stream` (NULL: the batch's stream) and
+ *   blocks until it finishes; results and latencies then refer to this run.
+ * efm_batch_result: network i's result (caller destroys it).  Its stats hold one
+ *   summary entry (parents, children, emitted).  Errors: EFM_EINVAL before a run
+ *   or for a bad index; EFM_ENOMEM / EFM_EOVERFLOW when that network overflowed a
+ *   capacity or the exact arithmetic.
+ * efm_batch_latency: ns[i] = device time from network i's start to its end
+ *   (device wall clock), for count entries.
+ * efm_batch_config_get: the tile shape in use. */
+typedef struct efm_batch efm_batch;
+typedef struct {
+  int32_t waves_per_network;   /* waves of the workgroup that runs one network */
+  int32_t networks_per_cu;     /* persistent workgroups per compute unit */
+} efm_batch_config;
+
+efm_status efm_batch_create(const efm_network *const *nets, const int32_t *targets, int32_t count,
+                            const efm_enum_opts *opts, efm_batch **out);
+efm_status efm_batch_run(efm_batch *batch, void *stream);
+efm_status efm_batch_result(const efm_batch *batch, int32_t i, efm_result **out);
+efm_status efm_batch_latency(const efm_batch *batch, int64_t *ns);
+efm_status efm_batch_config_get(const efm_batch *batch, efm_batch_config *cfg);
+efm_status efm_batch_destroy(efm_batch *batch);
 
 const char *efm_status_string(efm_status s);
 const char *efm_last_error(void);

@@ -9,13 +9,13 @@
 #include <vector>
 
 #include "../../include/efm.h"
-#include "efm_internal.h"
+#include "efm_host.h"
 
 using efm::u64;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
 
 efm_status fail(efm_status code, const char *fmt, ...) {
   char buf[512];
@@ -47,68 +47,21 @@ u64 splitmix64(u64 &state) {
 }
 
 // supported (reaction words, metabolite words) instantiations
-const int kShapes[][2] = {{1, 1}, {1, 2}, {2, 1}, {2, 2}, {2, 4}, {4, 1}, {4, 2}, {4, 4},
-                          {8, 2}, {8, 4}, {8, 8}, {16, 4}, {16, 8}, {16, 16}};
+static const int kShapes[][2] = {{1, 1}, {1, 2}, {2, 1}, {2, 2}, {2, 4}, {4, 1}, {4, 2}, {4, 4},
+                                 {8, 2}, {8, 4}, {8, 8}, {16, 4}, {16, 8}, {16, 16}};
 
-}  // namespace
-
-struct efm_network {
-  int m = 0, n = 0, mi = 0, W = 0, Wt = 0, MWt = 0;
-  std::vector<int32_t> S;
-  std::vector<uint8_t> rev, ext;
-  std::vector<int> int_row;   // internal metabolite -> row of S
-  void *blob = nullptr;
-  efm::DevNet dn{};
-};
-
-struct efm_result {
-  int W = 0, n = 0;
-  uint32_t status = 0;
-  int64_t count = 0;
-  std::vector<u64> keys;
-  std::vector<int64_t> flux;
-  std::vector<efm_level_stats> levels;
-};
-
-extern "C" {
-
-const char *efm_last_error(void) { return g_err.c_str(); }
-
-const char *efm_status_string(efm_status s) {
-  switch (s) {
-    case EFM_OK: return "ok";
-    case EFM_EINVAL: return "invalid argument";
-    case EFM_ENOMEM: return "workspace or capacity too small";
-    case EFM_EDEVICE: return "HIP error";
-    case EFM_EOVERFLOW: return "integer overflow";
-    default: return "unknown status";
-  }
+bool choose_shape(int W, int MW, int *Wt, int *MWt) {
+  for (auto &sh : kShapes)
+    if (sh[0] >= W && sh[1] >= MW) { *Wt = sh[0]; *MWt = sh[1]; return true; }
+  return false;
 }
 
-efm_status efm_network_create(int32_t n_met, int32_t n_rxn, const int32_t *S, const uint8_t *reversible,
-                              const uint8_t *external, efm_network **out) {
-  if (!S || !reversible || !external || !out) return fail(EFM_EINVAL, "null pointer");
-  if (n_met <= 0 || n_rxn <= 0 || n_rxn > EFM_MAX_RXN)
-    return fail(EFM_EINVAL, "bad dimensions %d x %d (reactions must be 1..%d)", n_met, n_rxn, EFM_MAX_RXN);
-  efm_network *N = new (std::nothrow) efm_network;
-  if (!N) return fail(EFM_ENOMEM, "host allocation failed");
-  N->m = n_met;
-  N->n = n_rxn;
-  N->S.assign(S, S + (size_t)n_met * n_rxn);
-  N->rev.assign(reversible, reversible + n_rxn);
-  N->ext.assign(external, external + n_met);
-  for (int i = 0; i < n_met; ++i)
-    if (!N->ext[i]) N->int_row.push_back(i);
-  N->mi = (int)N->int_row.size();
-  N->W = (n_rxn + 63) / 64;
-  const int MW = std::max(1, (N->mi + 63) / 64);
-  if (N->mi > 1024) {
-    delete N;
-    return fail(EFM_EINVAL, "%d internal metabolites (at most 1024)", (int)N->mi);
-  }
-  for (auto &sh : kShapes)
-    if (sh[0] >= N->W && sh[1] >= MW) { N->Wt = sh[0]; N->MWt = sh[1]; break; }
-  const int n = n_rxn, mi = N->mi, Wt = N->Wt, MWt = N->MWt;
+
+// Device tables of one network at the given padded widths, laid out in one host
+// buffer (offsets of the parts in `offs`).  Used for single networks and, at a
+// common width, for every member of a batch.
+void build_tables(const efm_network *N, int Wt, int MWt, std::vector<char> &host, std::vector<size_t> &offs) {
+  const int n = N->n, mi = N->mi;
 
   // host tables
   std::vector<u64> prodM((size_t)n * MWt), consM((size_t)n * MWt), revM((size_t)n * MWt),
@@ -168,42 +121,123 @@ efm_status efm_network_create(int32_t n_met, int32_t n_rxn, const int32_t *S, co
   u64 st = 0x5EEDF00DCAFEull;
   for (int r = 0; r < n; ++r) zob[r] = splitmix64(st);
 
-  // one device blob
-  struct Part { const void *src; size_t bytes; size_t off; };
-  std::vector<Part> parts = {
-      {prodM.data(), prodM.size() * 8, 0}, {consM.data(), consM.size() * 8, 0},
-      {revM.data(), revM.size() * 8, 0},   {touchM.data(), touchM.size() * 8, 0},
-      {fwdR.data(), fwdR.size() * 8, 0},   {bwdR.data(), bwdR.size() * 8, 0},
-      {allR.data(), allR.size() * 8, 0},   {nbrR.data(), nbrR.size() * 8, 0},
-      {revb.data(), revb.size() * 8, 0},   {Sint.data(), Sint.size() * 4, 0},
-      {zob.data(), zob.size() * 8, 0},     {ent.data(), ent.size() * 4, 0},
-      {nnz.data(), nnz.size() * 4, 0},     {oddM.data(), oddM.size() * 8, 0}};
+  struct Part { const void *src; size_t bytes; };
+  const Part parts[] = {
+      {prodM.data(), prodM.size() * 8}, {consM.data(), consM.size() * 8},
+      {revM.data(), revM.size() * 8},   {touchM.data(), touchM.size() * 8},
+      {fwdR.data(), fwdR.size() * 8},   {bwdR.data(), bwdR.size() * 8},
+      {allR.data(), allR.size() * 8},   {nbrR.data(), nbrR.size() * 8},
+      {revb.data(), revb.size() * 8},   {Sint.data(), Sint.size() * 4},
+      {zob.data(), zob.size() * 8},     {ent.data(), ent.size() * 4},
+      {nnz.data(), nnz.size() * 4},     {oddM.data(), oddM.size() * 8}};
+  offs.clear();
   size_t total = 0;
-  for (auto &p : parts) { p.off = total; total += align256(p.bytes); }
-  hipError_t e = hipMalloc(&N->blob, total);
-  if (e != hipSuccess) {
-    delete N;
-    return fail(EFM_EDEVICE, "hipMalloc(%zu) failed: %s", total, hipGetErrorString(e));
-  }
-  for (auto &p : parts) {
-    e = hipMemcpy((char *)N->blob + p.off, p.src, p.bytes, hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-      (void)hipFree(N->blob);
-      delete N;
-      return fail(EFM_EDEVICE, "hipMemcpy failed: %s", hipGetErrorString(e));
-    }
-  }
-  auto at = [&](int i) { return (const u64 *)((char *)N->blob + parts[i].off); };
-  efm::DevNet &d = N->dn;
-  d.n = n; d.mi = mi; d.Wt = Wt; d.MWt = MWt;
+  for (const auto &p : parts) { offs.push_back(total); total += align256(p.bytes); }
+  host.assign(total, 0);
+  for (size_t i = 0; i < sizeof(parts) / sizeof(parts[0]); ++i) memcpy(host.data() + offs[i], parts[i].src, parts[i].bytes);
+}
+
+efm::DevNet bind_tables(const efm_network *N, int Wt, int MWt, char *base, const std::vector<size_t> &offs) {
+  auto at = [&](int i) { return (const u64 *)(base + offs[i]); };
+  efm::DevNet d{};
+  d.n = N->n; d.mi = N->mi; d.Wt = Wt; d.MWt = MWt;
   d.rxn_prodM = at(0); d.rxn_consM = at(1); d.rxn_revM = at(2); d.rxn_touchM = at(3);
   d.met_fwdR = at(4); d.met_bwdR = at(5); d.met_allR = at(6); d.rxn_nbrR = at(7);
   d.rev_bits = at(8);
-  d.Sint = (const int32_t *)((char *)N->blob + parts[9].off);
+  d.Sint = (const int32_t *)(base + offs[9]);
   d.zob = at(10);
-  d.rxn_ent = (const uint32_t *)((char *)N->blob + parts[11].off);
-  d.rxn_nnz = (const int32_t *)((char *)N->blob + parts[12].off);
+  d.rxn_ent = (const uint32_t *)(base + offs[11]);
+  d.rxn_nnz = (const int32_t *)(base + offs[12]);
   d.rxn_oddM = at(13);
+  return d;
+}
+
+
+// Fill a result from found pathways: keys SoA (word w of pathway i at
+// fk[w * cnt + i], Wt words) and their nonzero fluxes in key order
+// (ff[i * ffstride + j] for the j-th reaction).  Sorted canonically, dense.
+void assemble(efm_result *R, int Wt, const u64 *fk, int64_t cnt, const int64_t *ff, int ffstride) {
+  const int W = R->W, n = R->n;
+  std::vector<int64_t> order(cnt);
+  for (int64_t i = 0; i < cnt; ++i) order[i] = i;
+  std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+    for (int w = Wt - 1; w >= 0; --w) {
+      const u64 x = fk[(size_t)w * cnt + a], y = fk[(size_t)w * cnt + b];
+      if (x != y) return x < y;
+    }
+    return false;
+  });
+  R->count = cnt;
+  R->keys.assign((size_t)cnt * W, 0);
+  R->flux.assign((size_t)cnt * n, 0);
+  for (int64_t i = 0; i < cnt; ++i) {
+    const int64_t src = order[i];
+    int j = 0;
+    for (int w = 0; w < Wt; ++w) {
+      u64 bits = fk[(size_t)w * cnt + src];
+      if (w < W) R->keys[(size_t)i * W + w] = bits;
+      while (bits) {
+        const int r = w * 64 + __builtin_ctzll(bits);
+        bits &= bits - 1;
+        R->flux[(size_t)i * n + r] = ff[(size_t)src * ffstride + j];
+        j++;
+      }
+    }
+  }
+}
+
+extern "C" {
+
+const char *efm_last_error(void) { return g_err.c_str(); }
+
+const char *efm_status_string(efm_status s) {
+  switch (s) {
+    case EFM_OK: return "ok";
+    case EFM_EINVAL: return "invalid argument";
+    case EFM_ENOMEM: return "workspace or capacity too small";
+    case EFM_EDEVICE: return "HIP error";
+    case EFM_EOVERFLOW: return "integer overflow";
+    default: return "unknown status";
+  }
+}
+
+efm_status efm_network_create(int32_t n_met, int32_t n_rxn, const int32_t *S, const uint8_t *reversible,
+                              const uint8_t *external, efm_network **out) {
+  if (!S || !reversible || !external || !out) return fail(EFM_EINVAL, "null pointer");
+  if (n_met <= 0 || n_rxn <= 0 || n_rxn > EFM_MAX_RXN)
+    return fail(EFM_EINVAL, "bad dimensions %d x %d (reactions must be 1..%d)", n_met, n_rxn, EFM_MAX_RXN);
+  efm_network *N = new (std::nothrow) efm_network;
+  if (!N) return fail(EFM_ENOMEM, "host allocation failed");
+  N->m = n_met;
+  N->n = n_rxn;
+  N->S.assign(S, S + (size_t)n_met * n_rxn);
+  N->rev.assign(reversible, reversible + n_rxn);
+  N->ext.assign(external, external + n_met);
+  for (int i = 0; i < n_met; ++i)
+    if (!N->ext[i]) N->int_row.push_back(i);
+  N->mi = (int)N->int_row.size();
+  N->W = (n_rxn + 63) / 64;
+  const int MW = std::max(1, (N->mi + 63) / 64);
+  if (N->mi > 1024) {
+    delete N;
+    return fail(EFM_EINVAL, "%d internal metabolites (at most 1024)", (int)N->mi);
+  }
+  choose_shape(N->W, MW, &N->Wt, &N->MWt);
+  std::vector<char> host;
+  std::vector<size_t> offs;
+  build_tables(N, N->Wt, N->MWt, host, offs);
+  hipError_t e = hipMalloc(&N->blob, host.size());
+  if (e != hipSuccess) {
+    delete N;
+    return fail(EFM_EDEVICE, "hipMalloc(%zu) failed: %s", host.size(), hipGetErrorString(e));
+  }
+  e = hipMemcpy(N->blob, host.data(), host.size(), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(N->blob);
+    delete N;
+    return fail(EFM_EDEVICE, "hipMemcpy failed: %s", hipGetErrorString(e));
+  }
+  N->dn = bind_tables(N, N->Wt, N->MWt, (char *)N->blob, offs);
   *out = N;
   return EFM_OK;
 }
@@ -488,7 +522,6 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
   R->status = status;
   R->levels = stats;
   {
-    const int W = N->W;
     std::vector<u64> fk((size_t)Wt * std::max<int64_t>(nfound, 1));
     std::vector<int64_t> ff((size_t)std::max<int64_t>(nfound, 1) * efm::kMaxDepth);
     for (int w = 0; w < Wt && nfound > 0; ++w)
@@ -496,32 +529,7 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
                        hipMemcpyDeviceToHost));
     if (nfound > 0)
       HIPCHK(hipMemcpy(ff.data(), L.fflux, (size_t)nfound * efm::kMaxDepth * 8, hipMemcpyDeviceToHost));
-    std::vector<int64_t> order(nfound);
-    for (int64_t i = 0; i < nfound; ++i) order[i] = i;
-    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
-      for (int w = Wt - 1; w >= 0; --w) {
-        const u64 x = fk[(size_t)w * nfound + a], y = fk[(size_t)w * nfound + b];
-        if (x != y) return x < y;
-      }
-      return false;
-    });
-    R->count = nfound;
-    R->keys.assign((size_t)nfound * W, 0);
-    R->flux.assign((size_t)nfound * n, 0);
-    for (int64_t i = 0; i < nfound; ++i) {
-      const int64_t src = order[i];
-      int j = 0;
-      for (int w = 0; w < Wt; ++w) {
-        u64 bits = fk[(size_t)w * nfound + src];
-        if (w < W) R->keys[(size_t)i * W + w] = bits;
-        while (bits) {
-          const int r = w * 64 + __builtin_ctzll(bits);
-          bits &= bits - 1;
-          R->flux[(size_t)i * n + r] = ff[(size_t)src * efm::kMaxDepth + j];
-          j++;
-        }
-      }
-    }
+    assemble(R, Wt, fk.data(), nfound, ff.data(), efm::kMaxDepth);
   }
 
 done:

@@ -20,186 +20,9 @@
 //                (Definition 2) and the emission of the pathway;
 //   select_*     radix selection of the frontier cap's smallest keys;
 //   materialize  the next frontier's keys (SoA) and hashes.
-#include "efm_internal.h"
+#include "efm_wave.h"
 
 namespace efm {
-
-#define DEVI __device__ __forceinline__
-
-// ------------------------------------------------------------------ wave helpers
-DEVI int lane_id() { return __lane_id(); }
-
-DEVI u64 lanes_below(int lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
-
-// Append `val` to `list` for every lane with pred set; one atomic per wave.
-// Must be called by all lanes of the wave (converged control flow).
-DEVI void wave_append(bool pred, u64 *list, u64 *counter, u64 val, int64_t cap, u64 *flags) {
-  u64 mask = __ballot(pred);
-  if (mask == 0) return;
-  int lane = lane_id();
-  int leader = __ffsll((long long)mask) - 1;
-  u64 base = 0;
-  if (lane == leader) base = atomicAdd(counter, (u64)__popcll(mask));
-  base = __shfl(base, leader);
-  if (pred) {
-    u64 idx = base + (u64)__popcll(mask & lanes_below(lane));
-    if ((int64_t)idx < cap) list[idx] = val;
-    else atomicOr(flags, (u64)kFlagQueueOverflow);
-  }
-}
-
-DEVI void wave_count(bool pred, u64 *counter) {
-  u64 mask = __ballot(pred);
-  if (mask != 0 && lane_id() == __ffsll((long long)mask) - 1) atomicAdd(counter, (u64)__popcll(mask));
-}
-
-// Wave-private staging of list appends in LDS (128 entries): one global atomic per
-// flush instead of one per wave and step.  `n` is wave-uniform.
-constexpr int kWaveBuf = 128;
-struct WaveBuf {
-  u64 *lds;
-  int n;
-};
-
-DEVI void wbuf_flush(WaveBuf &b, u64 *list, u64 *counter, int64_t cap, u64 *flags) {
-  if (b.n == 0) return;
-  const int lane = lane_id();
-  __threadfence_block();
-  u64 base = 0;
-  if (lane == 0) base = atomicAdd(counter, (u64)b.n);
-  base = __shfl(base, 0);
-  for (int i = lane; i < b.n; i += 64) {
-    const u64 idx = base + (u64)i;
-    if ((int64_t)idx < cap) list[idx] = b.lds[i];
-    else atomicOr(flags, (u64)kFlagQueueOverflow);
-  }
-  __threadfence_block();
-  b.n = 0;
-}
-
-DEVI void wbuf_push(WaveBuf &b, bool pred, u64 val, u64 *list, u64 *counter, int64_t cap, u64 *flags) {
-  const u64 mask = __ballot(pred);
-  const int cnt = __popcll(mask);
-  if (cnt == 0) return;
-  if (b.n + cnt > kWaveBuf) wbuf_flush(b, list, counter, cap, flags);
-  if (pred) b.lds[b.n + __popcll(mask & lanes_below(lane_id()))] = val;
-  b.n += cnt;
-}
-
-// Block-wide sum of per-thread counts into global counters (end of kernel; every
-// thread of the block must call it).
-template <int NC>
-DEVI void block_counts(u64 (&v)[NC], u64 *counters, const int (&slot)[NC]) {
-  __shared__ u64 acc[NC];
-  if (threadIdx.x < NC) acc[threadIdx.x] = 0;
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < NC; ++c) {
-    u64 t = v[c];
-    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
-    if (lane_id() == 0 && t) atomicAdd(&acc[c], t);
-  }
-  __syncthreads();
-  if (threadIdx.x < NC && acc[threadIdx.x]) atomicAdd(&counters[cslot(slot[threadIdx.x])], acc[threadIdx.x]);
-}
-
-DEVI int wave_max_int(int v) {
-  for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-  return v;
-}
-
-DEVI u64 wave_or(u64 v) {
-  for (int off = 32; off > 0; off >>= 1) v |= __shfl_xor(v, off);
-  return v;
-}
-
-// 64x64 bit-matrix transpose across the wave: on entry lane j holds row j, on
-// exit lane b holds bit b of every lane's entry row (bit j = entry lane j, bit b).
-DEVI u64 wave_transpose64(u64 a) {
-  const int lane = lane_id();
-  const u64 masks[6] = {0x00000000FFFFFFFFull, 0x0000FFFF0000FFFFull, 0x00FF00FF00FF00FFull,
-                        0x0F0F0F0F0F0F0F0Full, 0x3333333333333333ull, 0x5555555555555555ull};
-#pragma unroll
-  for (int st = 0; st < 6; ++st) {
-    const int j = 32 >> st;
-    const u64 m = masks[st];
-    const u64 other = __shfl_xor(a, j);
-    a = (lane & j) ? ((a & ~m) | ((other & ~m) >> j)) : ((a & m) | ((other & m) << j));
-  }
-  return a;
-}
-
-DEVI i128 shfl_i128(i128 v, int src) {
-  unsigned __int128 u = (unsigned __int128)v;
-  u64 lo = (u64)u, hi = (u64)(u >> 64);
-  lo = __shfl(lo, src);
-  hi = __shfl(hi, src);
-  return (i128)(((unsigned __int128)hi << 64) | lo);
-}
-
-DEVI i128 shfl_xor_i128(i128 v, int off) {
-  unsigned __int128 u = (unsigned __int128)v;
-  u64 lo = (u64)u, hi = (u64)(u >> 64);
-  lo = __shfl_xor(lo, off);
-  hi = __shfl_xor(hi, off);
-  return (i128)(((unsigned __int128)hi << 64) | lo);
-}
-
-// ------------------------------------------------------------- modular arithmetic
-DEVI uint32_t mulmod(uint32_t a, uint32_t b) {
-  u64 t = (u64)a * b;                       // < 2^62
-  t = (t & kPrime) + (t >> 31);             // < 2^32
-  t = (t & kPrime) + (t >> 31);             // <= 2^31
-  return (uint32_t)(t >= kPrime ? t - kPrime : t);
-}
-DEVI uint32_t submod(uint32_t a, uint32_t b) { return a >= b ? a - b : a + kPrime - b; }
-DEVI uint32_t powmod(uint32_t a, uint32_t e) {
-  uint32_t r = 1;
-  while (e) {
-    if (e & 1) r = mulmod(r, a);
-    a = mulmod(a, a);
-    e >>= 1;
-  }
-  return r;
-}
-DEVI uint32_t tomod(int32_t s) {
-  int64_t v = s % (int64_t)kPrime;
-  return (uint32_t)(v < 0 ? v + kPrime : v);
-}
-
-// ---------------------------------------------------------- exact 128-bit helpers
-// Stored matrix entries stay below 2^63 in magnitude, so a product of two fits in
-// 126 bits and a difference of two products in 127 bits.  Anything larger raises
-// the overflow flag (reported as EFM_EOVERFLOW).
-constexpr i128 kSafe = (i128)1 << 63;
-DEVI i128 iabs(i128 a) { return a < 0 ? -a : a; }
-DEVI bool safe(i128 a) { return a < kSafe && a > -kSafe; }
-DEVI i128 gcd_i128(i128 a, i128 b) {
-  a = iabs(a);
-  b = iabs(b);
-  while (b != 0) {
-    i128 t = a % b;
-    a = b;
-    b = t;
-  }
-  return a;
-}
-
-// j-th set bit (0-based) of a W-word key, or -1
-template <int W>
-DEVI int select_bit(const u64 *Q, int j) {
-#pragma unroll
-  for (int w = 0; w < W; ++w) {
-    int c = __popcll(Q[w]);
-    if (j < c) {
-      u64 x = Q[w];
-      for (int t = 0; t < j; ++t) x &= x - 1;
-      return w * 64 + __builtin_ctzll(x);
-    }
-    j -= c;
-  }
-  return -1;
-}
 
 // ------------------------------------------------------------------------ expand
 // Table entry: tag(7) | fingerprint(14) | parent(32) | reaction(11).  A slot whose
@@ -590,156 +413,7 @@ __global__ __launch_bounds__(256) void rank_kernel(DevNet net, DevLevel L, int p
       }
     }
 
-    int kq = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) kq += __popcll(Q[w]);
-    const int col = lane < kq ? select_bit<W>(Q, lane) : -1;
-    u64 tm[MW];
-#pragma unroll
-    for (int q = 0; q < MW; ++q) tm[q] = col >= 0 ? net.rxn_touchM[(int64_t)col * MW + q] : 0ull;
-
-    // Singleton peeling: a row that only one live column touches forces that
-    // column's flux to zero, so column and row leave the matrix and the rank
-    // drops by exactly one.  Q is independent iff what remains is, and it is
-    // independent outright once r's column is peeled (P is independent).
-    bool alive = col >= 0;
-    while (true) {
-      u64 once[MW], multi[MW];
-#pragma unroll
-      for (int q = 0; q < MW; ++q) { once[q] = alive ? tm[q] : 0ull; multi[q] = 0ull; }
-      for (int off = 32; off > 0; off >>= 1) {
-#pragma unroll
-        for (int q = 0; q < MW; ++q) {
-          const u64 o2 = __shfl_xor(once[q], off), m2 = __shfl_xor(multi[q], off);
-          multi[q] = multi[q] | m2 | (once[q] & o2);
-          once[q] = (once[q] | o2) & ~multi[q];
-        }
-      }
-      u64 hit = 0;
-#pragma unroll
-      for (int q = 0; q < MW; ++q) hit |= tm[q] & once[q];
-      const bool peel = alive && hit != 0;
-      if (__ballot(peel) == 0) break;
-      alive = alive && !peel;
-    }
-    const bool r_alive = __ballot(alive && col == r) != 0;
-    const int ncore = __popcll(__ballot(alive));
-    u64 T[MW];
-#pragma unroll
-    for (int q = 0; q < MW; ++q) T[q] = wave_or(alive ? tm[q] : 0ull);
-    int nrows = 0;
-#pragma unroll
-    for (int q = 0; q < MW; ++q) nrows += __popcll(T[q]);
-
-    bool indep = !r_alive;
-    if (!L.debug_prime && !L.no_gf2 && r_alive && nrows >= ncore) {
-      // GF(2) certificate: columns independent modulo 2 are independent over the
-      // rationals.  Lane b holds, for the core row q*64+b, the bit mask of the
-      // columns whose coefficient there is odd; XOR elimination over the columns.
-      u64 om[MW], rowm[MW];
-      bool used[MW];
-#pragma unroll
-      for (int q = 0; q < MW; ++q) {
-        om[q] = alive ? net.rxn_oddM[(int64_t)col * MW + q] : 0ull;
-        rowm[q] = wave_transpose64(om[q]);
-        used[q] = !((T[q] >> lane) & 1ull);
-      }
-      u64 cols = __ballot(alive);
-      bool ok = true;
-      while (cols) {
-        const int c = __ffsll((long long)cols) - 1;
-        cols &= cols - 1;
-        int pq = -1, pl = -1;
-#pragma unroll
-        for (int q = 0; q < MW; ++q) {
-          if (pq < 0) {
-            const u64 cand = __ballot(!used[q] && ((rowm[q] >> c) & 1ull));
-            if (cand) { pq = q; pl = __ffsll((long long)cand) - 1; }
-          }
-        }
-        if (pq < 0) { ok = false; break; }
-        u64 prow = 0;
-#pragma unroll
-        for (int q = 0; q < MW; ++q) {
-          if (q == pq) {
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)rowm[q], pl);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(rowm[q] >> 32), pl);
-            prow = ((u64)hi << 32) | lo;
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < MW; ++q) {
-          const bool me = (q == pq) && (lane == pl);
-          if (!me && ((rowm[q] >> c) & 1ull)) rowm[q] ^= prow;
-          if (me) used[q] = true;
-        }
-      }
-      indep = ok;
-    }
-    if (!L.debug_prime && r_alive && nrows >= ncore && !indep) {
-      // this lane's column entries
-      uint32_t ent[kMaxEnt];
-      int nnz = alive ? net.rxn_nnz[col] : 0;
-      const bool dense = nnz < 0;
-#pragma unroll
-      for (int e = 0; e < kMaxEnt; ++e) ent[e] = (e < nnz) ? net.rxn_ent[(int64_t)col * kMaxEnt + e] : 0xFFFF0000u;
-      // The basis lives in registers (lane j holds column j of every basis row) in
-      // reduced row-echelon form without normalisation: row b has a nonzero pivot
-      // value d_b in its pivot column and every other row has a 0 there.  A new
-      // row x0 is reduced fraction-free, x <- d_b x - (sigma f_b) row_b over the
-      // pivots where x0 itself is nonzero (f_b = x0[pc_b], sigma = product of the
-      // d_b used so far), which leaves x a nonzero multiple of the exact
-      // reduction.  No modular inverse is needed.
-      uint32_t B[kMaxDepth];
-#pragma unroll
-      for (int t = 0; t < kMaxDepth; ++t) B[t] = 0;
-      int nb = 0;
-      int rowof = -1;              // lane c: the basis row whose pivot column is c
-#pragma unroll
-      for (int q = 0; q < MW; ++q) {
-        u64 bits = T[q];
-        while (bits && !indep) {
-          const int i = q * 64 + __builtin_ctzll(bits);
-          bits &= bits - 1;
-          int32_t c = 0;
-          if (dense) {
-            c = net.Sint[(int64_t)i * net.n + col];
-          } else {
-#pragma unroll
-            for (int e = 0; e < kMaxEnt; ++e)
-              if ((int)(ent[e] >> 16) == i) c = (int32_t)(int16_t)(ent[e] & 0xFFFFu);
-          }
-          const uint32_t x0 = tomod(c);
-          uint32_t x = x0, sigma = 1;
-          u64 hits = __ballot(x0 != 0 && rowof >= 0);
-          while (hits) {
-            const int pc = __ffsll((long long)hits) - 1;
-            hits &= hits - 1;
-            const int bidx = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_readlane(rowof, pc));
-            const uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)x0, pc);
-            const uint32_t rb = B[bidx];
-            const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)rb, pc);
-            x = submod(mulmod(d, x), mulmod(mulmod(sigma, f), rb));
-            sigma = mulmod(sigma, d);
-          }
-          const u64 nz = __ballot(x != 0);
-          if (nz) {
-            const int pc = __ffsll((long long)nz) - 1;
-            const uint32_t dn = (uint32_t)__builtin_amdgcn_readlane((int)x, pc);
-            for (int bb = 0; bb < nb; ++bb) {
-              const uint32_t rb = B[bb];
-              const uint32_t cb = (uint32_t)__builtin_amdgcn_readlane((int)rb, pc);
-              if (cb) B[bb] = submod(mulmod(dn, rb), mulmod(cb, x));
-            }
-            B[nb] = x;
-            if (lane == pc) rowof = nb;
-            nb++;
-            if (nb == ncore) indep = true;
-          }
-        }
-      }
-    }
-    if (L.debug_prime) indep = false;
+    const bool indep = L.debug_prime ? false : wave_rank_child<W, MW>(net, Q, r, L.no_gf2 != 0);
     n_indep += (indep && lane == 0) ? 1 : 0;
     n_capped += (indep && !keep_indep && lane == 0) ? 1 : 0;
     wbuf_push(bsurv, indep && keep_indep && lane == 0, ref, L.surv, &L.counters[cslot(kSurv)], L.ucap,
@@ -755,9 +429,6 @@ __global__ __launch_bounds__(256) void rank_kernel(DevNet net, DevLevel L, int p
 }
 
 // ------------------------------------------------------------------------- exact
-// One wave per child.  Lane j owns column j of the dense matrix S_int[T, Q] kept in
-// global scratch (row-major, 64 entries per row); entries of other columns travel
-// by lane shuffles only.
 template <int W, int MW>
 __global__ __launch_bounds__(64) void exact_kernel(DevNet net, DevLevel L) {
   const int lane = lane_id();
@@ -773,66 +444,13 @@ __global__ __launch_bounds__(64) void exact_kernel(DevNet net, DevLevel L) {
 #pragma unroll
     for (int w = 0; w < W; ++w)
       Q[w] = L.keys[(int64_t)w * L.fcap + p] | ((r >> 6) == w ? (1ull << (r & 63)) : 0ull);
-    int kq = 0;
-#pragma unroll
-    for (int w = 0; w < W; ++w) kq += __popcll(Q[w]);
-    const bool mine = lane < kq;
-    const int col = mine ? select_bit<W>(Q, lane) : -1;
-    u64 T[MW];
-#pragma unroll
-    for (int q = 0; q < MW; ++q) T[q] = wave_or(col >= 0 ? net.rxn_touchM[(int64_t)col * MW + q] : 0ull);
-
-    // load the column
-    int R = 0;
-#pragma unroll
-    for (int q = 0; q < MW; ++q) {
-      u64 bits = T[q];
-      while (bits) {
-        const int i = q * 64 + __builtin_ctzll(bits);
-        bits &= bits - 1;
-        M[(size_t)R * 64 + lane] = mine ? (i128)net.Sint[(int64_t)i * net.n + col] : (i128)0;
-        R++;
-      }
-    }
-
-    // fraction-free elimination (Bareiss): after the step on pivot row t every
-    // entry below is a (t+2)-minor, so the division by the previous pivot is exact
-    bool ovf = false;
-    int rank = 0;
-    int pivreg = -1;               // lane t holds the pivot column of row t
-    i128 prev = 1;
-    for (int c = 0; c < kq && rank < R; ++c) {
-      int piv = -1;
-      if (lane == c)
-        for (int i = rank; i < R; ++i)
-          if (M[(size_t)i * 64 + lane] != 0) { piv = i; break; }
-      piv = __shfl(piv, c);
-      if (piv < 0) continue;
-      if (piv != rank) {
-        const i128 a = M[(size_t)piv * 64 + lane];
-        M[(size_t)piv * 64 + lane] = M[(size_t)rank * 64 + lane];
-        M[(size_t)rank * 64 + lane] = a;
-      }
-      const i128 pv = shfl_i128(M[(size_t)rank * 64 + lane], c);
-      const i128 top = M[(size_t)rank * 64 + lane];
-      for (int i = rank + 1; i < R; ++i) {
-        // every row below is updated, also when f = 0: the entries must become minors
-        const i128 f = shfl_i128(M[(size_t)i * 64 + lane], c);
-        if (lane >= c && mine) {
-          const i128 a = M[(size_t)i * 64 + lane];
-          if (!safe(a) || !safe(top) || !safe(pv) || !safe(f)) ovf = true;
-          else M[(size_t)i * 64 + lane] = (pv * a - f * top) / prev;
-        }
-      }
-      if (lane == rank) pivreg = c;
-      prev = pv;
-      rank++;
-    }
-    if (__ballot(ovf)) {
+    int64_t vout = 0;
+    const int outcome = wave_exact_child<W, MW>(net, Q, L.Sx, M, vout);
+    if (outcome == kExactOverflow) {
       if (lane == 0) atomicOr(&L.counters[cslot(kFlags)], (u64)kFlagIntOverflow);
       continue;
     }
-    if (rank == kq) {                      // the modular test was fooled: independent
+    if (outcome == kExactIndependent) {
       if (lane == 0) {
         atomicAdd(&L.counters[cslot(kIndep)], 1ull);
         if (keep_indep) {
@@ -845,66 +463,11 @@ __global__ __launch_bounds__(64) void exact_kernel(DevNet net, DevLevel L) {
       }
       continue;
     }
-    if (rank != kq - 1) continue;          // cannot happen for an independent parent
-
-    // the free column
-    bool piv_here = false;
-    for (int t = 0; t < rank; ++t) piv_here = piv_here || (__shfl(pivreg, t) == lane);
-    const u64 freem = __ballot(mine && !piv_here);
-    const int fcol = __ffsll((long long)freem) - 1;
-
-    // integer back substitution, v_f = 1, partial vector kept primitive
-    i128 v = lane == fcol ? (i128)1 : (i128)0;
-    for (int t = rank - 1; t >= 0 && !ovf; --t) {
-      const int pc = __shfl(pivreg, t);
-      const i128 a = M[(size_t)t * 64 + lane];
-      i128 term = 0;
-      if (lane > pc && mine && v != 0 && a != 0) {
-        if (!safe(a) || !safe(v)) ovf = true;
-        else term = a * v;
-      }
-      i128 sum = term;
-      for (int off = 32; off > 0; off >>= 1) {
-        const i128 o = shfl_xor_i128(sum, off);
-        if (iabs(sum) >= ((i128)1 << 125) || iabs(o) >= ((i128)1 << 125)) ovf = true;
-        sum += o;
-      }
-      ovf = __ballot(ovf) != 0;
-      if (ovf) break;
-      const i128 pt = shfl_i128(a, pc);
-      const i128 g = gcd_i128(sum, pt);
-      const i128 mult = iabs(pt) / g;
-      if (lane > pc && mult != 1) {
-        if (!safe(v) || !safe(mult)) ovf = true;
-        else v *= mult;
-      }
-      if (lane == pc) v = pt > 0 ? -(sum / g) : (sum / g);
-      i128 G = iabs(v);
-      for (int off = 32; off > 0; off >>= 1) G = gcd_i128(G, shfl_xor_i128(G, off));
-      if (G > 1) v /= G;
-      ovf = __ballot(ovf) != 0;
-    }
-    if (ovf) {
-      if (lane == 0) atomicOr(&L.counters[cslot(kFlags)], (u64)kFlagIntOverflow);
-      continue;
-    }
-
-    // Definition 2 and the target: full support, one sign on irreversible
-    // reactions (made positive), S[x,:] v > 0
-    if (__ballot(mine && v == 0) != 0) continue;
-    const bool irr = mine && !((net.rev_bits[col >> 6] >> (col & 63)) & 1ull);
-    const u64 posm = __ballot(irr && v > 0), negm = __ballot(irr && v < 0);
-    if (posm && negm) continue;
-    i128 prod = mine ? (i128)L.Sx[col] * v : (i128)0;
-    for (int off = 32; off > 0; off >>= 1) prod += shfl_xor_i128(prod, off);
-    int sgn = posm ? 1 : (negm ? -1 : (prod > 0 ? 1 : -1));
-    if (sgn < 0) { v = -v; prod = -prod; }
-    if (prod <= 0) continue;
-    const i128 lim = (i128)1 << 63;
-    if (__ballot(v >= lim || v < -lim) != 0) {
-      if (lane == 0) atomicOr(&L.counters[cslot(kFlags)], (u64)kFlagIntOverflow);
-      continue;
-    }
+    if (outcome != kExactEmit) continue;
+    int kq = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) kq += __popcll(Q[w]);
+    const bool mine = lane < kq;
     u64 slot = 0;
     if (lane == 0) slot = atomicAdd(&L.counters[cslot(kFound)], 1ull);
     slot = __shfl(slot, 0);
@@ -915,7 +478,7 @@ __global__ __launch_bounds__(64) void exact_kernel(DevNet net, DevLevel L) {
 #pragma unroll
     for (int w = 0; w < W; ++w)
       if (lane == w) L.fkeys[(int64_t)w * L.ecap + slot] = Q[w];
-    if (mine) L.fflux[(int64_t)slot * kMaxDepth + lane] = (int64_t)v;
+    if (mine) L.fflux[(int64_t)slot * kMaxDepth + lane] = vout;
     if (lane == 0) atomicAdd(&L.counters[cslot(kEmitted)], 1ull);
   }
 }

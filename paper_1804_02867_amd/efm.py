@@ -17,12 +17,14 @@ LIB_PATH = os.path.join(_HERE, "libefm.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, EOVERFLOW = 0, -1, -2, -3, -4
 COMPLETE, DEPTH_CAPPED, FRONTIER_TRUNCATED = 0, 1, 2
-OPT_NO_PRUNE, OPT_EXACT_RANK, OPT_TIME_KERNELS, OPT_NO_GF2 = 1, 2, 4, 8
+OPT_NO_PRUNE, OPT_EXACT_RANK, OPT_TIME_KERNELS, OPT_NO_GF2, OPT_AUTOTUNE = 1, 2, 4, 8, 16
 MAX_DEPTH = 64
 
 EXPORTS = ["efm_network_create", "efm_network_destroy", "efm_workspace_query", "efm_enumerate",
            "efm_result_info", "efm_result_stats", "efm_result_bitsets", "efm_result_fluxes",
-           "efm_result_destroy", "efm_status_string", "efm_last_error"]
+           "efm_result_destroy", "efm_status_string", "efm_last_error",
+           "efm_batch_create", "efm_batch_run", "efm_batch_result", "efm_batch_latency",
+           "efm_batch_config_get", "efm_batch_destroy"]
 
 
 class EnumOpts(ctypes.Structure):
@@ -174,3 +176,92 @@ def enumerate_pathways(net: Network, target: int, depth_cap=0, frontier_cap=0, u
         return Result(keys, flux, int(status.value), levels)
     finally:
         lib.efm_result_destroy(res)
+
+
+# ------------------------------------------------------------------- batches
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("waves_per_network", ctypes.c_int32), ("networks_per_cu", ctypes.c_int32)]
+
+
+def _load_batch(lib):
+    if getattr(lib, "_batch_sigs", False):
+        return lib
+    P, I32 = ctypes.c_void_p, ctypes.c_int32
+    sig = {
+        "efm_batch_create": ([P, P, I32, ctypes.POINTER(EnumOpts), ctypes.POINTER(P)], I32),
+        "efm_batch_run": ([P, P], I32),
+        "efm_batch_result": ([P, I32, ctypes.POINTER(P)], I32),
+        "efm_batch_latency": ([P, P], I32),
+        "efm_batch_config_get": ([P, ctypes.POINTER(BatchConfig)], I32),
+        "efm_batch_destroy": ([P], I32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    lib._batch_sigs = True
+    return lib
+
+
+def _fetch(lib, res, n):
+    cnt, W, status, nl = ctypes.c_int64(), ctypes.c_int32(), ctypes.c_uint32(), ctypes.c_int32()
+    _check(lib.efm_result_info(res, ctypes.byref(cnt), ctypes.byref(W), ctypes.byref(status), ctypes.byref(nl)))
+    keys = np.zeros((cnt.value, W.value), np.uint64)
+    flux = np.zeros((cnt.value, n), np.int64)
+    _check(lib.efm_result_bitsets(res, keys.ctypes.data, keys.size))
+    _check(lib.efm_result_fluxes(res, flux.ctypes.data, flux.size))
+    arr = (LevelStats * max(nl.value, 1))()
+    _check(lib.efm_result_stats(res, arr, nl.value))
+    levels = [{f: getattr(arr[i], f) for f, _ in LevelStats._fields_} for i in range(nl.value)]
+    return Result(keys, flux, int(status.value), levels)
+
+
+class Batch:
+    """efm_batch_*: many networks in one persistent launch, replayed as a HIP graph."""
+
+    def __init__(self, nets, targets, depth_cap=0, frontier_cap=0, unique_cap=0, found_cap=0, flags=0):
+        _require_gpu()
+        self._lib = _load_batch(load())
+        self.nets = list(nets)
+        self.n = [g.n for g in self.nets]
+        handles = (ctypes.c_void_p * len(self.nets))(*[g._h.value for g in self.nets])
+        tg = np.ascontiguousarray(targets, dtype=np.int32)
+        opts = make_opts(depth_cap, frontier_cap, unique_cap, found_cap, flags)
+        h = ctypes.c_void_p()
+        _check(self._lib.efm_batch_create(ctypes.cast(handles, ctypes.c_void_p), tg.ctypes.data, len(self.nets),
+                                          ctypes.byref(opts), ctypes.byref(h)))
+        self._h = h
+
+    def run(self, stream=None):
+        st = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(self._lib.efm_batch_run(self._h, st))
+
+    def config(self):
+        c = BatchConfig()
+        _check(self._lib.efm_batch_config_get(self._h, ctypes.byref(c)))
+        return c.waves_per_network, c.networks_per_cu
+
+    def result(self, i) -> Result:
+        res = ctypes.c_void_p()
+        _check(self._lib.efm_batch_result(self._h, int(i), ctypes.byref(res)))
+        try:
+            return _fetch(self._lib, res, self.n[i])
+        finally:
+            self._lib.efm_result_destroy(res)
+
+    def latency_ns(self) -> np.ndarray:
+        out = np.zeros(len(self.nets), np.int64)
+        _check(self._lib.efm_batch_latency(self._h, out.ctypes.data))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.efm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
