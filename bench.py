@@ -34,6 +34,66 @@ def expand_bytes(level: dict, W: int) -> float:
     return level["parents"] * (8 * W + 8) + level["children"] * 8 + level["unique"] * 8
 
 
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_batch_networks(count):
+    """Seeded batch networks, generated in worker processes (call before any GPU
+    use: the workers are forked)."""
+    import concurrent.futures as cf
+    from paper_1804_02867_amd import netgen
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        return list(ex.map(netgen.batch_member, range(count), chunksize=64))
+
+
+def batch_sweep(args, nets, efm, torch):
+    """The batched serving-style sweep: seeded networks of uneven size, one target
+    each, in one persistent launch replayed as a HIP graph."""
+    import numpy as np
+    targets = [n.targets[0] for n in nets]
+    handles = [efm.Network(*n.arrays()) for n in nets]
+    log(f"batch: {len(nets)} networks uploaded; creating (autotune)")
+    b = efm.Batch(handles, targets, depth_cap=args.batch_depth_cap, frontier_cap=args.batch_frontier_cap,
+                  unique_cap=args.batch_unique_cap, flags=efm.OPT_AUTOTUNE)
+    log(f"batch: tile {b.config()}; warm-up sweep")
+    b.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        b.run()
+        log(f"batch: sweep {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    res = [b.result(i) for i in range(len(nets))]
+    pathways = sum(r.count for r in res)
+    parents = sum(r.levels[0]["parents"] for r in res)
+    lat = b.latency_ns() / 1e6
+    cfg = b.config()
+    b.close()
+    out = {"workload": f"{len(nets)} batch networks (m 10-80, n 15-120 log-uniform, seeds 100000+i), "
+                       f"depth cap {args.batch_depth_cap}, frontier cap {args.batch_frontier_cap}",
+           "ms_per_sweep": dt * 1e3, "networks_per_s": len(nets) / dt, "pathways_per_s": pathways / dt,
+           "pathways_per_sweep": pathways, "frontier_items_per_s": parents / dt,
+           "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+           "tile": {"waves_per_network": cfg[0], "networks_per_cu": cfg[1]}}
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        k = 0
+        cpu_paths = 0
+        while k < len(nets) and time.perf_counter() - t < 10.0:
+            S, rev, ext = nets[k].arrays()
+            cpu_paths += oracle.enumerate_pathways(S, rev, ext, targets[k], depth_cap=args.batch_depth_cap,
+                                                   frontier_cap=args.batch_frontier_cap).count
+            k += 1
+        cdt = time.perf_counter() - t
+        out["cpu_baseline"] = {"networks_per_s": k / cdt, "pathways_per_s": cpu_paths / cdt, "cores": 1,
+                               "kind": "oracle", "sample": f"first {k} networks of the sweep ({cdt:.1f} s)"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,11 +104,22 @@ def main():
     ap.add_argument("--frontier-cap", type=int, default=1 << 20)
     ap.add_argument("--targets", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-count", type=int, default=4096)
+    ap.add_argument("--batch-depth-cap", type=int, default=12)
+    ap.add_argument("--batch-frontier-cap", type=int, default=2048)
+    ap.add_argument("--batch-unique-cap", type=int, default=1 << 19)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see the sharding paragraph of the design notes)", file=sys.stderr)
         sys.exit(2)
+
+    batch_nets = None
+    if not args.no_batch:
+        t = time.perf_counter()
+        batch_nets = make_batch_networks(args.batch_count)
+        log(f"batch: generated {len(batch_nets)} networks in {time.perf_counter() - t:.1f} s")
 
     import numpy as np
     import torch
@@ -76,10 +147,12 @@ def main():
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    log("central: warm-up done")
     t0 = time.perf_counter()
     results = []
-    for _ in range(args.steps):
+    for k in range(args.steps):
         results.append(step())
+        log(f"central: step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
 
@@ -95,6 +168,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
+        log("central: CPU oracle sample")
         import oracle
         ncores = 1
         sample_targets = targets[:3]
@@ -136,6 +210,8 @@ def main():
                      "alg_bytes_per_launch": bytes_exp / max(nlaunch, 1)},
         "cpu_baseline": cpu,
     }
+    if not args.no_batch:
+        line["batch"] = batch_sweep(args, batch_nets, efm, torch)
     print(json.dumps(line), flush=True)
 
 

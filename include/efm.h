@@ -73,8 +73,9 @@ typedef struct {
 } efm_enum_opts;
 
 #define EFM_OPT_NO_PRUNE 1u      /* skip the found-set minimality prune (result unchanged) */
-#define EFM_OPT_EXACT_RANK 2u    /* decide every rank test in exact integer arithmetic instead of
-                                    modulo a prime first (slower; result unchanged) */
+#define EFM_OPT_EXACT_RANK 2u    /* decide every row-closed child by fraction-free 128-bit
+                                    elimination, skipping the modular tests and the modular
+                                    null-vector lift (slower; result unchanged) */
 #define EFM_OPT_NO_GF2 8u        /* skip the modulo-2 independence certificate, so every undecided
                                     rank test runs modulo the prime (result unchanged) */
 #define EFM_OPT_AUTOTUNE 16u     /* batch only: time candidate tile shapes once at creation and keep

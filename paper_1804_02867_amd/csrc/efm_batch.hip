@@ -78,6 +78,7 @@ struct BatchArgs {
   char *arena;
   size_t slice_bytes;
   int mi_max;
+  int lds_rows;        // basis rows per wave in LDS: min(depth cap, largest internal-row count)
   u64 *queue;
   u64 *out_keys;       // [out_cap][W]
   int64_t *out_flux;   // [out_cap][dstride]
@@ -97,7 +98,9 @@ DEVI bool slice_insert(u64 *table, u64 tmask, u64 tag, u64 h, u64 p, int r, cons
   const u64 entry = (tag << 57) | (((h >> 50) & 0x3FFFull) << 43) | ((p & 0xFFFFFFFFull) << 11) | (u64)r;
   const u64 fp = (h >> 50) & 0x3FFFull;
   u64 pos = h & tmask;
-  for (u64 probe = 0; probe <= tmask; ++probe) {
+  const u64 max_probe = tmask < kMaxProbe ? tmask + 1 : kMaxProbe;
+  for (u64 probe = 0; probe < max_probe; ++probe) {
+    if (*(volatile uint32_t *)err) return false;     // the level already failed
     u64 cur = __hip_atomic_load(&table[pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     while ((cur >> 57) != tag) {
       const u64 prev = atomicCAS(&table[pos], cur, entry);
@@ -130,6 +133,7 @@ DEVI void lds_push(int *cnt, u64 *list, int64_t cap, u64 val, uint32_t *err) {
 
 template <int W, int MW>
 __global__ __launch_bounds__(512) void batch_kernel(BatchArgs A) {
+  extern __shared__ uint32_t Bdyn[];    // per wave: depth_cap rows of 64 basis entries
   __shared__ int s_ni;
   __shared__ int s_cnt[kNumLds];
   __shared__ uint32_t s_err, s_status;
@@ -192,6 +196,7 @@ __global__ __launch_bounds__(512) void batch_kernel(BatchArgs A) {
       // ---- expand: one thread per parent
       u64 my_children = 0;
       for (int64_t p = tid; p < nparents; p += bs) {
+        if (*(volatile uint32_t *)&s_err) break;        // a capacity overflowed: stop early
         u64 P[W], cand[W], T[MW];
 #pragma unroll
         for (int w = 0; w < W; ++w) { P[w] = ka[(int64_t)w * A.fcap + p]; cand[w] = 0; }
@@ -316,7 +321,8 @@ __global__ __launch_bounds__(512) void batch_kernel(BatchArgs A) {
           kq += __popcll(Q[w]);
         }
         int64_t vout = 0;
-        const int outcome = wave_exact_child<W, MW>(net, Q, B.Sx, M, vout);
+        const int outcome = wave_exact_child<W, MW>(net, Q, B.Sx, M, Bdyn + (size_t)wave * A.lds_rows * 64, vout,
+                                                    A.exact_only != 0);
         if (outcome == kExactOverflow) {
           if (lane == 0) atomicOr(&s_err, (uint32_t)kFlagIntOverflow);
         } else if (outcome == kExactIndependent) {
@@ -454,7 +460,8 @@ __global__ void batch_reset_kernel(u64 *queue, u64 *out_count) {
 
 template <int W, int MW>
 static void do_batch(const BatchArgs &A, int grid, int block, hipStream_t s) {
-  hipLaunchKernelGGL((batch_kernel<W, MW>), dim3(grid), dim3(block), 0, s, A);
+  const size_t lds = (size_t)(block / 64) * A.lds_rows * 64 * sizeof(uint32_t);
+  hipLaunchKernelGGL((batch_kernel<W, MW>), dim3(grid), dim3(block), lds, s, A);
 }
 
 static hipError_t launch_batch(int Wt, int MWt, const BatchArgs &A, int grid, int block, hipStream_t s) {
@@ -511,8 +518,16 @@ int64_t next_pow2_b(int64_t x) {
   return p;
 }
 
+// largest waves-per-network whose LDS basis rows fit in 48 KB
+int max_waves(const efm_batch *b) {
+  int w = 8;
+  while (w > 1 && (size_t)w * b->args.lds_rows * 64 * 4 > 48 * 1024) w >>= 1;
+  return w;
+}
+
 efm_status capture(efm_batch *b) {
   efm_status rc = EFM_OK;
+  b->cfg.waves_per_network = std::min(b->cfg.waves_per_network, max_waves(b));
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   const int block = 64 * b->cfg.waves_per_network;
@@ -659,6 +674,7 @@ efm_status efm_batch_create(const efm_network *const *nets, const int32_t *targe
     A.no_gf2 = (o.flags & EFM_OPT_NO_GF2) ? 1 : 0;
     A.exact_only = (o.flags & EFM_OPT_EXACT_RANK) ? 1 : 0;
     A.mi_max = mi_max;
+    A.lds_rows = std::max(1, std::min(D, mi_max));
     A.dstride = b->dstride;
     A.out_cap = std::max<int64_t>(1 << 16, std::min<int64_t>((int64_t)count * A.ecap, (int64_t)1 << 22));
     // arena for the largest tile shape tried: 8 waves, 8 networks per CU
@@ -693,6 +709,7 @@ efm_status efm_batch_create(const efm_network *const *nets, const int32_t *targe
     float best = 1e30f;
     efm_batch_config best_cfg = b->cfg;
     for (auto &c : cand) {
+      if (c[0] > max_waves(b)) continue;
       b->cfg.waves_per_network = c[0];
       b->cfg.networks_per_cu = c[1];
       if ((rc = capture(b)) != EFM_OK) goto bad;

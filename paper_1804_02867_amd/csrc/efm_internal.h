@@ -15,6 +15,10 @@ typedef __int128 i128;
 constexpr uint32_t kPrime = 2147483647u;
 constexpr int kMaxDepth = 64;      // support sizes handled (a wave holds one column per lane)
 constexpr int kPruneMax = 8192;    // found pathways scanned by the minimality prune
+// Longest probe sequence of a table insert.  Tables are kept at most half full,
+// where linear probing essentially never runs this long; a longer run is
+// reported as a full table instead of scanning it.
+constexpr unsigned long long kMaxProbe = 4096;
 
 // Counter slots (u64) in device memory, reset per level except kFound.
 enum Counter {

@@ -37,7 +37,8 @@ DEVI bool table_insert(const DevLevel &L, u64 tag, u64 h, u64 p, int r, const u6
   const u64 entry = make_entry(tag, h, p, r);
   const u64 fp = (h >> 50) & 0x3FFFull;
   u64 pos = h & L.tmask;
-  for (u64 probe = 0; probe <= L.tmask; ++probe) {
+  const u64 max_probe = L.tmask < kMaxProbe ? L.tmask + 1 : kMaxProbe;
+  for (u64 probe = 0; probe < max_probe; ++probe) {
     u64 cur = __hip_atomic_load(&L.table[pos], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     while ((cur >> 57) != tag) {
       u64 prev = atomicCAS(&L.table[pos], cur, entry);
@@ -431,6 +432,7 @@ __global__ __launch_bounds__(256) void rank_kernel(DevNet net, DevLevel L, int p
 // ------------------------------------------------------------------------- exact
 template <int W, int MW>
 __global__ __launch_bounds__(64) void exact_kernel(DevNet net, DevLevel L) {
+  __shared__ uint32_t Bl[kMaxDepth * 64];
   const int lane = lane_id();
   const int64_t nitems = min((int64_t)L.counters[cslot(kExactQ)], L.ucap);
   const bool keep_indep = L.level + 1 < L.depth_cap;
@@ -445,7 +447,7 @@ __global__ __launch_bounds__(64) void exact_kernel(DevNet net, DevLevel L) {
     for (int w = 0; w < W; ++w)
       Q[w] = L.keys[(int64_t)w * L.fcap + p] | ((r >> 6) == w ? (1ull << (r & 63)) : 0ull);
     int64_t vout = 0;
-    const int outcome = wave_exact_child<W, MW>(net, Q, L.Sx, M, vout);
+    const int outcome = wave_exact_child<W, MW>(net, Q, L.Sx, M, Bl, vout, L.debug_prime != 0);
     if (outcome == kExactOverflow) {
       if (lane == 0) atomicOr(&L.counters[cslot(kFlags)], (u64)kFlagIntOverflow);
       continue;

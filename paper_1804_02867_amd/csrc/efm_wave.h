@@ -165,15 +165,196 @@ DEVI bool wave_rank_child(const DevNet &net, const u64 *Q, int r, bool no_gf2) {
 }
 
 // Exact decision for a child Q that the modular test called dependent, by the
-// whole wave.  Lane j owns column j of the dense matrix S_int[rows of Q, Q] kept in
+// whole wave.  The modular lift above is tried first (unless bareiss_only); the
+// 128-bit elimination below decides what it cannot.  Lane j owns column j of the dense matrix S_int[rows of Q, Q] kept in
 // scratch M (row-major, 64 entries per row); entries of other columns travel by
 // lane shuffles only.  On kExactEmit, vout holds (in lane j) the primitive flux of
 // the j-th reaction of Q, signed as Definition 2 and the target require.
 enum ExactOutcome { kExactDrop = 0, kExactIndependent = 1, kExactEmit = 2, kExactOverflow = 3 };
 
+// ---- modular null vector with rational reconstruction (the common, cheap case)
+DEVI int64_t wave_sum_i64(int64_t v) {
+  for (int off = 32; off > 0; off >>= 1) v += (int64_t)__shfl_xor((long long)v, off);
+  return v;
+}
+DEVI int64_t gcd_i64(int64_t a, int64_t b) {
+  a = a < 0 ? -a : a;
+  b = b < 0 ? -b : b;
+  while (b) { const int64_t t = a % b; a = b; b = t; }
+  return a;
+}
+
+// The smallest fraction a/b (|a| <= 32767, 0 < b <= 32767) congruent to w modulo
+// 2^31-1, by the extended Euclidean algorithm stopped at the half-size remainder
+// (Wang's rational reconstruction).  Returns false when none exists.
+DEVI bool rational_reconstruct(uint32_t w, int64_t &a, int64_t &b) {
+  constexpr int64_t N = 32767;
+  int64_t r0 = kPrime, r1 = w, t0 = 0, t1 = 1;
+  while (r1 > N) {
+    const int64_t q = r0 / r1;
+    const int64_t r2 = r0 - q * r1, t2 = t0 - q * t1;
+    r0 = r1; r1 = r2; t0 = t1; t1 = t2;
+  }
+  if (t1 == 0 || t1 > N || t1 < -N) return false;
+  a = t1 < 0 ? -r1 : r1;
+  b = t1 < 0 ? -t1 : t1;
+  return gcd_i64(a, b) == 1;
+}
+
+// Definition 2 and the target on an exact null vector v (lane j: entry of the
+// j-th reaction): full support, one sign on the irreversible reactions (made
+// positive), S[x,:] v > 0.  |v| < 2^55.
+DEVI int wave_sign_target(const DevNet &net, const int32_t *Sx, bool mine, int col, int64_t v, int64_t &vout) {
+  if (__ballot(mine && v == 0) != 0) return kExactDrop;
+  const bool irr = mine && !((net.rev_bits[col >> 6] >> (col & 63)) & 1ull);
+  const u64 posm = __ballot(irr && v > 0), negm = __ballot(irr && v < 0);
+  if (posm && negm) return kExactDrop;
+  int64_t prod = wave_sum_i64(mine ? (int64_t)Sx[col] * v : 0);
+  const int sgn = posm ? 1 : (negm ? -1 : (prod > 0 ? 1 : -1));
+  if (sgn < 0) { v = -v; prod = -prod; }
+  if (prod <= 0) return kExactDrop;
+  vout = v;
+  return kExactEmit;
+}
+
+// Exact decision through arithmetic modulo 2^31-1: the null vector modulo p of
+// S_int[rows of Q, Q], lifted entry by entry by rational reconstruction, scaled
+// to a primitive integer vector and checked against S_int v = 0 in exact 64-bit
+// arithmetic.  A vector that passes is the exact null vector (the parent is
+// independent, so the null space has dimension one); anything else returns -1
+// and the caller falls back to 128-bit elimination.
 template <int W, int MW>
-DEVI int wave_exact_child(const DevNet &net, const u64 *Q, const int32_t *Sx, i128 *M, int64_t &vout) {
+DEVI int wave_exact_modp(const DevNet &net, const u64 *Q, const int32_t *Sx, uint32_t *Bl, int64_t &vout) {
   const int lane = lane_id();
+  int kq = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) kq += __popcll(Q[w]);
+  const bool mine = lane < kq;
+  const int col = mine ? select_bit<W>(Q, lane) : -1;
+  u64 T[MW];
+#pragma unroll
+  for (int q = 0; q < MW; ++q) T[q] = wave_or(col >= 0 ? net.rxn_touchM[(int64_t)col * MW + q] : 0ull);
+  uint32_t ent[kMaxEnt];
+  const int nnz = mine ? net.rxn_nnz[col] : 0;
+  const bool dense = nnz < 0;
+#pragma unroll
+  for (int e = 0; e < kMaxEnt; ++e) ent[e] = (e < nnz) ? net.rxn_ent[(int64_t)col * kMaxEnt + e] : 0xFFFF0000u;
+  auto coef = [&](int i) -> int32_t {
+    int32_t c = 0;
+    if (!mine) return 0;
+    if (dense) return net.Sint[(int64_t)i * net.n + col];
+#pragma unroll
+    for (int e = 0; e < kMaxEnt; ++e)
+      if ((int)(ent[e] >> 16) == i) c = (int32_t)(int16_t)(ent[e] & 0xFFFFu);
+    return c;
+  };
+
+  // reduced row-echelon basis modulo p, unnormalised (as in the rank test); basis
+  // row b lives in Bl[b * 64 + lane], each lane touching only its own column
+  int nb = 0, rowof = -1;
+#pragma unroll
+  for (int q = 0; q < MW; ++q) {
+    u64 bits = T[q];
+    while (bits) {
+      const int i = q * 64 + __builtin_ctzll(bits);
+      bits &= bits - 1;
+      const uint32_t x0 = tomod(coef(i));
+      uint32_t x = x0, sigma = 1;
+      u64 hits = __ballot(x0 != 0 && rowof >= 0);
+      while (hits) {
+        const int pc = __ffsll((long long)hits) - 1;
+        hits &= hits - 1;
+        const int bidx = __builtin_amdgcn_readfirstlane(__builtin_amdgcn_readlane(rowof, pc));
+        const uint32_t f = (uint32_t)__builtin_amdgcn_readlane((int)x0, pc);
+        const uint32_t rb = Bl[bidx * 64 + lane];
+        const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)rb, pc);
+        x = submod(mulmod(d, x), mulmod(mulmod(sigma, f), rb));
+        sigma = mulmod(sigma, d);
+      }
+      const u64 nz = __ballot(x != 0);
+      if (nz) {
+        if (nb >= kq) return -1;                 // cannot happen: rank <= columns
+        const int pc = __ffsll((long long)nz) - 1;
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_readlane((int)x, pc);
+        for (int bb = 0; bb < nb; ++bb) {
+          const uint32_t rb = Bl[bb * 64 + lane];
+          const uint32_t cb = (uint32_t)__builtin_amdgcn_readlane((int)rb, pc);
+          if (cb) Bl[bb * 64 + lane] = submod(mulmod(dn, rb), mulmod(cb, x));
+        }
+        Bl[nb * 64 + lane] = x;
+        if (lane == pc) rowof = nb;
+        nb++;
+      }
+    }
+  }
+  if (nb == kq) return kExactIndependent;     // independent modulo p, hence over the rationals
+  if (nb != kq - 1) return -1;
+  const int f = __ffsll((long long)__ballot(mine && rowof < 0)) - 1;
+  // Null vector modulo p without per-pivot inverses: with pivot values d_b and
+  // free-column entries e_b, v_f = prod d_b and v_pc(b) = -e_b prod_{b' != b} d_b'.
+  uint32_t dreg = 1, ereg = 0;     // lane b: d_b, e_b
+  for (int b = 0; b < nb; ++b) {
+    const uint32_t rb = Bl[b * 64 + lane];
+    const int pc = __ffsll((long long)__ballot(rowof == b)) - 1;
+    const uint32_t e = (uint32_t)__builtin_amdgcn_readlane((int)rb, f);
+    const uint32_t d = (uint32_t)__builtin_amdgcn_readlane((int)rb, pc);
+    if (lane == b) { dreg = d; ereg = e; }
+  }
+  uint32_t pre = 1, Dall = 1;      // lane b: product of d_b' for b' < b
+  for (int b = 0; b < nb; ++b) {
+    if (lane == b) pre = Dall;
+    Dall = mulmod(Dall, (uint32_t)__builtin_amdgcn_readlane((int)dreg, b));
+  }
+  uint32_t suf = 1, acc = 1;       // lane b: product of d_b' for b' > b
+  for (int b = nb - 1; b >= 0; --b) {
+    if (lane == b) suf = acc;
+    acc = mulmod(acc, (uint32_t)__builtin_amdgcn_readlane((int)dreg, b));
+  }
+  const uint32_t cb_ = mulmod(mulmod(pre, suf), ereg);   // lane b: e_b prod_{b' != b} d_b'
+  const uint32_t Dinv = powmod(Dall, kPrime - 2);
+  uint32_t vp = lane == f ? 1u : 0u;                      // entries divided by v_f = prod d_b
+  for (int b = 0; b < nb; ++b) {
+    const int pc = __ffsll((long long)__ballot(rowof == b)) - 1;
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)cb_, b);
+    if (lane == pc) vp = c ? mulmod(kPrime - c, Dinv) : 0u;
+  }
+  // lift: v_j / v_f = a_j / b_j, then clear denominators
+  int64_t a = 0, den = 1;
+  bool ok = !mine || rational_reconstruct(vp, a, den);
+  if (__ballot(!ok) != 0) return -1;
+  int64_t L = mine ? den : 1;
+  for (int off = 32; off > 0; off >>= 1) {
+    const int64_t o = (int64_t)__shfl_xor((long long)L, off);
+    const int64_t lg = L / gcd_i64(L, o);
+    if (lg > (((int64_t)1 << 40) / o)) { ok = false; L = 1; }
+    else L = lg * o;
+  }
+  if (__ballot(!ok) != 0) return -1;
+  int64_t v = mine ? a * (L / den) : 0;
+  int64_t g = v < 0 ? -v : v;
+  for (int off = 32; off > 0; off >>= 1) g = gcd_i64(g, (int64_t)__shfl_xor((long long)g, off));
+  if (g > 1) v /= g;
+  // exact check S_int v = 0 on every row of Q (|coef| < 2^15, |v| < 2^55)
+#pragma unroll
+  for (int q = 0; q < MW; ++q) {
+    u64 bits = T[q];
+    while (bits) {
+      const int i = q * 64 + __builtin_ctzll(bits);
+      bits &= bits - 1;
+      if (wave_sum_i64((int64_t)coef(i) * v) != 0) return -1;
+    }
+  }
+  return wave_sign_target(net, Sx, mine, col, v, vout);
+}
+
+template <int W, int MW>
+DEVI int wave_exact_child(const DevNet &net, const u64 *Q, const int32_t *Sx, i128 *M, uint32_t *Bl,
+                          int64_t &vout, bool bareiss_only = false) {
+  const int lane = lane_id();
+  if (!bareiss_only) {
+    const int fast = wave_exact_modp<W, MW>(net, Q, Sx, Bl, vout);
+    if (fast >= 0) return fast;
+  }
     int kq = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) kq += __popcll(Q[w]);
