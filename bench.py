@@ -56,7 +56,7 @@ def batch_sweep(args, nets, efm, torch):
     handles = [efm.Network(*n.arrays()) for n in nets]
     log(f"batch: {len(nets)} networks uploaded; creating (autotune)")
     b = efm.Batch(handles, targets, depth_cap=args.batch_depth_cap, frontier_cap=args.batch_frontier_cap,
-                  unique_cap=args.batch_unique_cap, flags=efm.OPT_AUTOTUNE)
+                  unique_cap=args.batch_unique_cap, found_cap=args.batch_found_cap, flags=efm.OPT_AUTOTUNE)
     log(f"batch: tile {b.config()}; warm-up sweep")
     b.run()
     torch.cuda.synchronize()
@@ -66,7 +66,12 @@ def batch_sweep(args, nets, efm, torch):
         log(f"batch: sweep {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / args.steps
-    res = [b.result(i) for i in range(len(nets))]
+    res, failed = [], 0
+    for i in range(len(nets)):
+        try:
+            res.append(b.result(i))
+        except efm.EfmError:
+            failed += 1                     # a capacity of this network overflowed
     pathways = sum(r.count for r in res)
     parents = sum(r.levels[0]["parents"] for r in res)
     lat = b.latency_ns() / 1e6
@@ -77,7 +82,8 @@ def batch_sweep(args, nets, efm, torch):
            "ms_per_sweep": dt * 1e3, "networks_per_s": len(nets) / dt, "pathways_per_s": pathways / dt,
            "pathways_per_sweep": pathways, "frontier_items_per_s": parents / dt,
            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
-           "tile": {"waves_per_network": cfg[0], "networks_per_cu": cfg[1]}}
+           "tile": {"waves_per_network": cfg[0], "networks_per_cu": cfg[1]},
+           "networks_over_capacity": failed}
     if not args.no_cpu_baseline:
         import oracle
         t = time.perf_counter()
@@ -109,6 +115,7 @@ def main():
     ap.add_argument("--batch-depth-cap", type=int, default=12)
     ap.add_argument("--batch-frontier-cap", type=int, default=2048)
     ap.add_argument("--batch-unique-cap", type=int, default=1 << 19)
+    ap.add_argument("--batch-found-cap", type=int, default=1 << 15)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "

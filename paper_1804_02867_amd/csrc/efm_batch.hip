@@ -44,7 +44,7 @@ struct SliceLayout {
 __host__ __device__ inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 __host__ __device__ inline SliceLayout slice_layout(int W, int64_t fcap, int64_t ucap, int64_t tcap, int64_t ecap,
-                                                    int mi_max, int waves) {
+                                                    int dstride, int mi_max, int waves) {
   SliceLayout s{};
   size_t off = 0;
   auto take = [&](size_t b) { size_t o = off; off += al256(b); return o; };
@@ -58,7 +58,7 @@ __host__ __device__ inline SliceLayout slice_layout(int W, int64_t fcap, int64_t
   s.exq = take((size_t)ucap * 8);
   s.sel = take((size_t)ucap);
   s.fkeys = take((size_t)W * ecap * 8);
-  s.fflux = take((size_t)ecap * kMaxDepth * 8);
+  s.fflux = take((size_t)ecap * dstride * 8);
   s.xs = take((size_t)waves * (mi_max > 0 ? mi_max : 1) * 64 * sizeof(i128));
   s.total = off;
   return s;
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(512) void batch_kernel(BatchArgs A) {
   const int tid = threadIdx.x, bs = blockDim.x, lane = lane_id();
   const int wave = tid >> 6, nwaves = bs >> 6;
   char *base = A.arena + (size_t)blockIdx.x * A.slice_bytes;
-  const SliceLayout lay = slice_layout(W, A.fcap, A.ucap, A.tcap, A.ecap, A.mi_max, nwaves);
+  const SliceLayout lay = slice_layout(W, A.fcap, A.ucap, A.tcap, A.ecap, A.dstride, A.mi_max, nwaves);
   u64 *ka = (u64 *)(base + lay.ka), *ha = (u64 *)(base + lay.ha);
   u64 *kb = (u64 *)(base + lay.kb), *hb = (u64 *)(base + lay.hb);
   u64 *table = (u64 *)(base + lay.table);
@@ -338,7 +338,7 @@ __global__ __launch_bounds__(512) void batch_kernel(BatchArgs A) {
 #pragma unroll
             for (int w = 0; w < W; ++w)
               if (lane == w) fkeys[(int64_t)w * A.ecap + slot] = Q[w];
-            if (lane < kq) fflux[(int64_t)slot * kMaxDepth + lane] = vout;
+            if (lane < kq) fflux[(int64_t)slot * A.dstride + lane] = vout;
           } else if (lane == 0) {
             atomicOr(&s_err, (uint32_t)kFlagFoundOverflow);
           }
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(512) void batch_kernel(BatchArgs A) {
       for (int i = tid; i < nfound; i += bs) {
 #pragma unroll
         for (int w = 0; w < W; ++w) A.out_keys[(s_off + i) * W + w] = fkeys[(int64_t)w * A.ecap + i];
-        for (int j = 0; j < A.dstride; ++j) A.out_flux[(s_off + i) * A.dstride + j] = fflux[(int64_t)i * kMaxDepth + j];
+        for (int j = 0; j < A.dstride; ++j) A.out_flux[(s_off + i) * A.dstride + j] = fflux[(int64_t)i * A.dstride + j];
       }
     }
     __syncthreads();
@@ -537,7 +537,7 @@ efm_status capture(efm_batch *b) {
   {
     const int grid = std::min(b->count, cus * b->cfg.networks_per_cu);
     efm::BatchArgs A = b->args;
-    A.slice_bytes = efm::slice_layout(b->Wt, A.fcap, A.ucap, A.tcap, A.ecap, A.mi_max, b->cfg.waves_per_network).total;
+    A.slice_bytes = efm::slice_layout(b->Wt, A.fcap, A.ucap, A.tcap, A.ecap, A.dstride, A.mi_max, b->cfg.waves_per_network).total;
     b->args = A;
     BCHK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     hipError_t le = efm::launch_batch(b->Wt, b->MWt, A, grid, block, b->stream);
@@ -684,7 +684,7 @@ efm_status efm_batch_create(const efm_network *const *nets, const int32_t *targe
     int khz = 100000;
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0) khz = 100000;
     b->ns_per_tick = 1e6 / (double)khz;
-    const size_t slice_max = efm::slice_layout(Wt, A.fcap, A.ucap, A.tcap, A.ecap, mi_max, 8).total;
+    const size_t slice_max = efm::slice_layout(Wt, A.fcap, A.ucap, A.tcap, A.ecap, A.dstride, mi_max, 8).total;
     const int grid_max = std::min(count, cus * 8);
     BCHK(hipMalloc(&b->arena, slice_max * grid_max));
     A.arena = (char *)b->arena;
