@@ -13,7 +13,9 @@ What it covers:
 * the sparse input of a partial pathway P: one unit entry per reaction of P at
   its relabelled position, and one entry per internal metabolite i with a
   non-zero imbalance count u_i = clamp(#{r in P: S_ir > 0} - #{r in P: S_ir < 0},
-  -7, 7), valued u_i / 8, at position in_bits + (relabelled i);
+  -7, 7): each metabolite owns two input rows, in_bits + 2 * (relabelled i) for a
+  surplus and the next one for a deficit, and the entry is |u_i| / 8 on the row of
+  its sign (so that one linear unit can sum the magnitudes);
 * the trace label of a partial pathway: 1 iff some elementary flux mode found by
   the plain traversal contains it (a sub-pathway that closes into a balanced one);
 * the three-layer perceptron  s = w3 . relu(W2^T relu(W1^T x + b1) + b2) + b3,
@@ -91,7 +93,8 @@ def features(S, ext, reactions, rpos, mpos, in_bits):
     """Sparse input of the partial pathway with reaction set `reactions`:
     a list of (row, code) pairs, reactions first in increasing reaction index,
     then internal metabolites in increasing internal index.  code 0 = a reaction
-    bit (value 1); code c in 1..15 = imbalance u = c - 8 (value u / 8)."""
+    bit (value 1); code c in 1..7 = an imbalance of magnitude c (value c / 8) on
+    the metabolite's surplus row (u > 0) or deficit row (u < 0)."""
     S = np.asarray(S)
     internal = [i for i in range(S.shape[0]) if not ext[i]]
     rs = sorted(set(int(r) for r in reactions))
@@ -105,7 +108,7 @@ def features(S, ext, reactions, rpos, mpos, in_bits):
                 c -= 1
         u = max(-7, min(7, c))
         if u != 0:
-            out.append((in_bits + int(mpos[k]), u + 8))
+            out.append((in_bits + 2 * int(mpos[k]) + (1 if u < 0 else 0), abs(u)))
     return out
 
 
@@ -120,7 +123,7 @@ def decode(words):
 
 
 def code_value(code):
-    return 1.0 if code == 0 else (code - 8) / 8.0
+    return 1.0 if code == 0 else code / 8.0
 
 
 def dense(records, F):

@@ -49,17 +49,18 @@ def test_relabel_unreached_last():
 def test_features_hand_worked():
     S, rev, ext = _net5()
     rpos, mpos = L.relabel(S, rev, ext, 4)
-    # P = {r0, r3}: bits r0 -> 2, r3 -> 0; A consumed once -> u = -1 (code 7) at 8 + 1
-    assert L.features(S, ext, [3, 0], rpos, mpos, 8) == [(2, 0), (0, 0), (9, 7)]
+    # P = {r0, r3}: bits r0 -> 2, r3 -> 0; A consumed once -> u = -1: magnitude 1 on
+    # A's deficit row 8 + 2 * 1 + 1
+    assert L.features(S, ext, [3, 0], rpos, mpos, 8) == [(2, 0), (0, 0), (11, 1)]
     # P = {r1, r3, r4}: every count cancels (signs are counted, not coefficients)
     assert L.features(S, ext, [1, 3, 4], rpos, mpos, 8) == [(1, 0), (0, 0), (3, 0)]
-    # P = {r0, r1, r2, r3}: A -3 (code 5), B +1 (code 9), C +1 (code 9)
+    # P = {r0, r1, r2, r3}: A -3 (deficit row 11), B +1 (surplus row 8), C +1 (surplus row 12)
     assert L.features(S, ext, [0, 1, 2, 3], rpos, mpos, 8) == [
-        (2, 0), (1, 0), (4, 0), (0, 0), (9, 5), (8, 9), (10, 9)]
+        (2, 0), (1, 0), (4, 0), (0, 0), (11, 3), (8, 1), (12, 1)]
 
 
 def test_features_clamp():
-    # metabolite M consumed by nine reactions: count -9 clamps to -7 (code 1)
+    # metabolite M consumed by nine reactions: count -9 clamps to -7 (deficit row, 7)
     S = np.zeros((11, 10), np.int64)
     for r in range(9):
         S[0, r] = -1
@@ -70,8 +71,8 @@ def test_features_clamp():
     rpos, mpos = L.relabel(S, np.zeros(10, np.uint8), ext, 10)
     ent = L.features(S, ext, range(9), rpos, mpos, 16)
     counts = [e for e in ent if e[0] >= 16]
-    assert (16 + mpos[0], 1) in counts
-    assert sum(1 for e in counts if e[1] == 9) == 9       # the nine products
+    assert (16 + 2 * mpos[0] + 1, 7) in counts
+    assert sum(1 for e in counts if e[1] == 1 and (e[0] - 16) % 2 == 0) == 9   # the nine products
     assert L.decode(L.encode(ent)) == ent
 
 
