@@ -100,6 +100,99 @@ def batch_sweep(args, nets, efm, torch):
     return out
 
 
+def learned_section(args, efm, torch):
+    """Learned vs plain: traces from the plain traversal of seeded training
+    networks, GPU training, then on held-out networks the exhaustive plain set,
+    the learned ordering and the canonical truncation at each budget."""
+    import numpy as np
+    from paper_1804_02867_amd import netgen
+    D, UC = args.learned_depth_cap, 1 << 27
+    t = time.perf_counter()
+    tr = efm.Traces(1024, 400, capacity=1 << 22)
+    runs = with_paths = 0
+    for i in range(args.learned_train):
+        net = netgen.learn_member(200000 + i)
+        g = efm.Network(*net.arrays())
+        for x in net.targets:
+            try:
+                info = tr.collect(g, x, depth_cap=D, unique_cap=UC, pos_max=1000, neg_per_pos=3.0, neg_min=500,
+                                  seed=i * 7 + x)
+            except efm.EfmError as e:
+                if "traces full" in str(e):
+                    break
+                continue                     # a capacity overflowed: this run gives no traces
+            runs += 1
+            with_paths += info["pathways"] > 0
+        if (i + 1) % 5 == 0:
+            log(f"learned: traces from {i + 1} networks")
+    collect_s = time.perf_counter() - t
+    nrec, npos = tr.info()
+    m = efm.Model(1024, 400, seed=args.seed)
+    tt = time.perf_counter()
+    st1 = m.train(tr, epochs=args.learned_epochs, batch=1024, lr=2e-3, seed=1)
+    st2 = m.train(tr, epochs=max(1, args.learned_epochs // 2), batch=1024, lr=4e-4, seed=2)
+    train_s = time.perf_counter() - tt
+    log(f"learned: {nrec} records trained in {train_s:.1f} s (loss {st1['loss_first']:.3f} -> {st2['loss_last']:.3f})")
+    tr.close()
+    budgets = [1 << int(b) for b in args.learned_budgets.split(",")]
+    first = netgen.learn_member(300000)
+    g0 = efm.Network(*first.arrays())
+    ws_plain = torch.empty(efm.workspace_bytes(g0, efm.make_opts(D, 0, UC, 0, 0)), dtype=torch.uint8, device="cuda")
+    ws_learn = torch.empty(max(efm.workspace_bytes(g0, efm.make_opts(D, B, UC, 0, efm.OPT_LEARNED)) for B in budgets),
+                           dtype=torch.uint8, device="cuda")
+    agg = {B: {"hits": 0, "canon_hits": 0, "t": 0.0, "t_canon": 0.0, "macro": [], "macro_canon": []}
+           for B in budgets}
+    t_plain, total, pairs = 0.0, 0, 0
+    for i in range(args.learned_eval):
+        net = netgen.learn_member(300000 + i)
+        g = efm.Network(*net.arrays())
+        for x in net.targets:
+            try:
+                t = time.perf_counter()
+                p = efm.enumerate_pathways(g, x, depth_cap=D, unique_cap=UC, workspace=ws_plain)
+                tp = time.perf_counter() - t
+            except efm.EfmError:
+                continue                     # exhaustive run too large for the capacity: no reference set
+            if p.keys.shape[0] == 0:
+                continue
+            P = {tuple(k) for k in p.keys.tolist()}
+            pairs += 1
+            total += len(P)
+            t_plain += tp
+            for B in budgets:
+                t = time.perf_counter()
+                lr = efm.enumerate_learned(g, x, B, m, depth_cap=D, unique_cap=UC, workspace=ws_learn)
+                tl = time.perf_counter() - t
+                t = time.perf_counter()
+                cn = efm.enumerate_pathways(g, x, depth_cap=D, frontier_cap=B, unique_cap=UC, workspace=ws_plain)
+                tc = time.perf_counter() - t
+                hl = len(P & {tuple(k) for k in lr.keys.tolist()})
+                hc = len(P & {tuple(k) for k in cn.keys.tolist()})
+                a = agg[B]
+                a["hits"] += hl
+                a["canon_hits"] += hc
+                a["t"] += tl
+                a["t_canon"] += tc
+                a["macro"].append(hl / len(P))
+                a["macro_canon"].append(hc / len(P))
+        log(f"learned: evaluated {i + 1} networks")
+    rows = []
+    for B in budgets:
+        a = agg[B]
+        rows.append({"budget": B, "recall": a["hits"] / max(total, 1), "recall_macro": float(np.mean(a["macro"] or [0])),
+                     "speedup_vs_plain": t_plain / max(a["t"], 1e-12), "learned_s": a["t"],
+                     "canonical_recall": a["canon_hits"] / max(total, 1),
+                     "canonical_recall_macro": float(np.mean(a["macro_canon"] or [0])), "canonical_s": a["t_canon"]})
+    return {"workload": f"learned ordering on power-law networks (40 internal metabolites, 60 + 4 reactions), "
+                        f"depth cap {D}; train seeds 200000..{200000 + args.learned_train - 1}, held-out seeds "
+                        f"300000..{300000 + args.learned_eval - 1}, every target with a non-empty exhaustive set",
+            "train": {"runs": runs, "runs_with_pathways": with_paths, "records": nrec, "positives": npos,
+                      "collect_s": collect_s, "train_s": train_s, "epochs": args.learned_epochs + max(1, args.learned_epochs // 2),
+                      "loss_first": st1["loss_first"], "loss_last": st2["loss_last"]},
+            "eval": {"pairs": pairs, "pathways": total, "plain_s": t_plain},
+            "budgets": rows, "target_recall": 0.99}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -116,6 +209,12 @@ def main():
     ap.add_argument("--batch-frontier-cap", type=int, default=2048)
     ap.add_argument("--batch-unique-cap", type=int, default=1 << 19)
     ap.add_argument("--batch-found-cap", type=int, default=1 << 15)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--learned-train", type=int, default=20)
+    ap.add_argument("--learned-eval", type=int, default=12)
+    ap.add_argument("--learned-epochs", type=int, default=8)
+    ap.add_argument("--learned-depth-cap", type=int, default=16)
+    ap.add_argument("--learned-budgets", default="14,16,18,20,22")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -179,7 +278,7 @@ def main():
         import oracle
         ncores = 1
         sample_targets = targets[:3]
-        cap = 2000
+        cap = 1000
         t = time.perf_counter()
         cpu_parents = 0
         for x in sample_targets:
@@ -219,6 +318,8 @@ def main():
     }
     if not args.no_batch:
         line["batch"] = batch_sweep(args, batch_nets, efm, torch)
+    if not args.no_learned:
+        line["learned"] = learned_section(args, efm, torch)
     print(json.dumps(line), flush=True)
 
 

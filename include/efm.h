@@ -82,6 +82,9 @@ typedef struct {
                                     the fastest */
 #define EFM_OPT_TIME_KERNELS 4u  /* record HIP events around every kernel launch on the stream and
                                     report per-level kernel times in efm_level_stats */
+#define EFM_OPT_LEARNED 32u      /* workspace layout of efm_enumerate_learned (adds one 4-byte score
+                                    per distinct child); pass it to efm_workspace_query when sizing
+                                    a workspace for that call */
 
 /* Per-level counters (level k = partial pathways of k reactions). */
 typedef struct {
@@ -96,7 +99,7 @@ typedef struct {
   double ms_expand;     /* kernel times on the stream (EFM_OPT_TIME_KERNELS only, else 0) */
   double ms_rank;
   double ms_exact;
-  double ms_select;
+  double ms_select;     /* truncation: scoring (learned ordering) and selection */
   double ms_materialize;
 } efm_level_stats;
 
@@ -179,6 +182,143 @@ efm_status efm_batch_result(const efm_batch *batch, int32_t i, efm_result **out)
 efm_status efm_batch_latency(const efm_batch *batch, int64_t *ns);
 efm_status efm_batch_config_get(const efm_batch *batch, efm_batch_config *cfg);
 efm_status efm_batch_destroy(efm_batch *batch);
+
+
+/* ------------------------------------------------------- learned ordering
+ * A three-layer perceptron scores partial pathways for whether they will close
+ * into an elementary pathway; efm_enumerate_learned keeps, at every level whose
+ * independent children exceed the budget, the `budget` best-scored ones (ties by
+ * canonical order) instead of the canonically smallest.  Every pathway it
+ * returns is still decided by the exact rank test, so the output is always a
+ * subset of the exhaustive result; with a budget at least as large as every
+ * level, it equals efm_enumerate's.  The ordering replaces the random choices of
+ * the paper's Algorithm 3 under the search budget its Theorem 1 discusses.
+ *
+ * Input of a partial pathway P of a network, for target x: reactions and
+ * internal metabolites are relabelled by breadth-first distance from the
+ * reactions that touch x (then decreasing degree, then index).  One entry per
+ * reaction of P (value 1 at its position, < in_bits) and one per internal
+ * metabolite i whose imbalance count u_i = clamp(#{r in P: S_ir > 0} -
+ * #{r in P: S_ir < 0}, -7, 7) is non-zero: metabolite position q owns rows
+ * in_bits + 2q (surplus, u_i > 0) and in_bits + 2q + 1 (deficit), and the entry
+ * is |u_i| / 8 on the row of its sign.  Entries are 16-bit words
+ * (row << 4) | code: code 0 = a reaction (value 1), code c in 1..7 = an
+ * imbalance of magnitude c (value c / 8).  At most EFM_FEAT_MAX entries.
+ *
+ * Model: s = w3 . relu(W2^T relu(W1^T x + b1) + b2) + b3 with F = in_bits +
+ * 2 * in_counts inputs and hidden = 256 units; fp32 master parameters, bf16 copies of
+ * W1, W2 and w3 used by the kernels, fp32 accumulation.  Parameter vector order:
+ * W1 [F][256] row-major, b1 [256], W2 [256 in][256 out], b2 [256], w3 [256], b3 [1].
+ * Loss: mean over the batch of pw*y*softplus(-s) + (1-y)*softplus(s); Adam.
+ */
+#define EFM_FEAT_MAX 512
+#define EFM_TRACE_WORDS 16   /* key words stored per trace record */
+
+typedef struct efm_model efm_model;
+typedef struct efm_traces efm_traces;
+
+typedef struct {
+  double neg_per_pos;    /* negatives kept per kept positive state at each level (<= 0: 4) */
+  int64_t neg_min;       /* negatives kept at least per level, when there are any (<= 0: 64) */
+  int64_t pos_max;       /* positives kept at most per level (<= 0: all) */
+  uint64_t seed;         /* sampling seed */
+} efm_trace_opts;
+
+typedef struct {
+  int64_t states;        /* frontier states seen (levels 2..) */
+  int64_t positives;     /* states contained in a pathway the plain run found (seen, not kept) */
+  int64_t recorded;      /* records appended */
+  int64_t pathways;      /* pathways the plain run found */
+  uint32_t status;       /* status flags of the plain run */
+  uint32_t reserved;
+} efm_trace_info;
+
+typedef struct {
+  int32_t epochs;        /* passes over the traces (<= 0: 1) */
+  int32_t batch;         /* records per step (<= 0: 1024), at most 65536 */
+  float lr;              /* Adam step size (<= 0: 1e-3) */
+  float beta1, beta2;    /* (<= 0: 0.9, 0.999) */
+  float eps;             /* (<= 0: 1e-8) */
+  float pos_weight;      /* weight of positive records (<= 0: #negatives / #positives) */
+  uint32_t reserved;
+  uint64_t seed;         /* shuffling seed */
+  void *stream;          /* hipStream_t (NULL = null stream) */
+} efm_train_opts;
+
+typedef struct {
+  int64_t steps;         /* Adam steps taken by this call */
+  double loss_first;     /* mean loss over the first epoch */
+  double loss_last;      /* mean loss over the last epoch */
+  double ms;             /* wall time of the call */
+} efm_train_stats;
+
+/* Traces: labelled partial pathways in model-input form, in device memory.
+ * efm_traces_create: room for `capacity` records.  EFM_EINVAL unless
+ *   0 < in_bits <= EFM_MAX_RXN, 0 < in_counts <= 1024, capacity > 0.
+ * efm_traces_info: records held and how many of them are positive.
+ * efm_trace_collect (Section 4.1 traversal used as a teacher): runs the plain
+ *   traversal of efm_enumerate with opts, then runs it again and, at every level
+ *   from the second, labels each frontier state 1 when a pathway found by the
+ *   first run contains it, keeps the positives (a hashed sample of pos_max when
+ *   there are more) and a hashed sample of the negatives (max(neg_min,
+ *   neg_per_pos * kept positives) per level), and appends them.  EFM_EINVAL when
+ *   the network does not fit in_bits / in_counts or a reaction touches more than
+ *   16 internal metabolites; EFM_ENOMEM
+ *   when the traces are full (records up to capacity are kept).
+ * efm_traces_append: records from the host (entries count x EFM_FEAT_MAX words,
+ *   lengths, labels 0/1); keys are stored as zero.
+ * efm_traces_fetch: copies records [first, first + count) to the host; any
+ *   pointer may be NULL (entries count x EFM_FEAT_MAX, keys count x
+ *   EFM_TRACE_WORDS). */
+efm_status efm_traces_create(int32_t in_bits, int32_t in_counts, int64_t capacity, efm_traces **out);
+efm_status efm_traces_destroy(efm_traces *tr);
+efm_status efm_traces_info(const efm_traces *tr, int64_t *count, int64_t *positives);
+efm_status efm_trace_collect(efm_traces *tr, const efm_network *net, int32_t target_met,
+                             const efm_enum_opts *opts, const efm_trace_opts *topts,
+                             efm_trace_info *info);
+efm_status efm_traces_append(efm_traces *tr, const uint16_t *entries, const uint16_t *lengths,
+                             const uint8_t *labels, int64_t count);
+efm_status efm_traces_fetch(const efm_traces *tr, int64_t first, int64_t count, uint16_t *entries,
+                            uint16_t *lengths, uint8_t *labels, uint64_t *keys);
+
+/* Model.  efm_model_create: hidden must be 256; weights uniform in +-sqrt(6/fan)
+ *   (fan 32 for W1, 256 otherwise) from a seeded generator, biases 0.
+ * efm_model_get_params / set_params: the fp32 parameter vector (len = n_params);
+ *   set_params also rounds the bf16 copies (to nearest even) and clears Adam.
+ * efm_model_save / load: a binary file (parameters, Adam moments and step).
+ * efm_model_score: logits of records [first, first + count) (host output).
+ * efm_model_score_keys: logits of partial pathways of `net` for target_met given as
+ *   bitsets (host, count x W words of the network), with the traversal's own
+ *   featurisation.
+ * efm_model_grad: mean loss and its gradient (host, n_params floats) over
+ *   records [first, first + count), count <= 65536, without an update.
+ * efm_model_train: Adam over all records, shuffled per epoch.
+ * All run on the null stream except train (opts->stream) and block until done. */
+efm_status efm_model_create(int32_t in_bits, int32_t in_counts, int32_t hidden, uint64_t seed,
+                            efm_model **out);
+efm_status efm_model_destroy(efm_model *model);
+efm_status efm_model_info(const efm_model *model, int64_t *n_params, int32_t *in_bits,
+                          int32_t *in_counts, int32_t *hidden);
+efm_status efm_model_get_params(const efm_model *model, float *dst, int64_t len);
+efm_status efm_model_set_params(efm_model *model, const float *src, int64_t len);
+efm_status efm_model_save(const efm_model *model, const char *path);
+efm_status efm_model_load(const char *path, efm_model **out);
+efm_status efm_model_score(const efm_model *model, const efm_traces *tr, int64_t first, int64_t count,
+                           float *scores);
+efm_status efm_model_score_keys(const efm_model *model, const efm_network *net, int32_t target_met,
+                                const uint64_t *keys, int64_t count, float *scores);
+efm_status efm_model_grad(const efm_model *model, const efm_traces *tr, int64_t first, int64_t count,
+                          float pos_weight, float *grad, double *loss);
+efm_status efm_model_train(efm_model *model, const efm_traces *tr, const efm_train_opts *opts,
+                           efm_train_stats *stats);
+
+/* efm_enumerate with frontier_cap = budget and the learned ordering of the
+ * truncation.  opts as for efm_enumerate (its frontier_cap is ignored); a
+ * caller-provided workspace must be sized by efm_workspace_query with
+ * EFM_OPT_LEARNED set.  Errors as efm_enumerate, plus EFM_EINVAL when the model's
+ * input does not fit the network or budget <= 0. */
+efm_status efm_enumerate_learned(const efm_network *net, int32_t target_met, int64_t budget,
+                                 const efm_model *model, const efm_enum_opts *opts, efm_result **out);
 
 const char *efm_status_string(efm_status s);
 const char *efm_last_error(void);

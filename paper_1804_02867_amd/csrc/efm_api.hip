@@ -258,7 +258,7 @@ struct Layout {
   int xwaves;
   size_t off_counters, off_hist, off_selst, off_root, off_sx, off_fa_keys, off_fa_hash, off_fb_keys, off_fb_hash,
       off_table, off_surv, off_rankq, off_parq, off_parmask, off_exactq, off_sel, off_skey, off_fkeys, off_fflux,
-      off_xs, total;
+      off_xs, off_sscore, total;
 };
 
 int64_t next_pow2(int64_t x) {
@@ -299,6 +299,7 @@ Layout make_layout(const efm_network *N, const efm_enum_opts *o) {
   L.off_fkeys = take((size_t)Wt * L.ecap * 8);
   L.off_fflux = take((size_t)L.ecap * efm::kMaxDepth * 8);
   L.off_xs = take((size_t)L.xwaves * std::max(N->mi, 1) * 64 * sizeof(efm::i128));
+  L.off_sscore = (o && (o->flags & EFM_OPT_LEARNED)) ? take((size_t)L.ucap * 4) : 0;
   L.total = off;
   return L;
 }
@@ -315,6 +316,23 @@ efm_status efm_workspace_query(const efm_network *net, const efm_enum_opts *opts
 
 efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_opts *opts,
                          efm_result **out) {
+  if (opts && (opts->flags & EFM_OPT_LEARNED)) {
+    efm_enum_opts o = *opts;
+    o.flags &= ~EFM_OPT_LEARNED;   // the score array is only used by efm_enumerate_learned
+    if (o.workspace && o.workspace_bytes < make_layout(N, opts).total)
+      return fail(EFM_ENOMEM, "workspace too small");
+    return enumerate_impl(N, target, &o, nullptr, out);
+  }
+  return enumerate_impl(N, target, opts, nullptr, out);
+}
+
+}  // extern "C"
+
+// The level loop shared by the plain traversal, the learned ordering (`hook`
+// scores the survivors when they exceed the frontier cap) and trace collection
+// (`hook` sees every new frontier).
+efm_status enumerate_impl(const efm_network *N, int32_t target, const efm_enum_opts *opts, LevelHook *hook,
+                          efm_result **out) {
   if (!N || !out) return fail(EFM_EINVAL, "null pointer");
   if (target < 0 || target >= N->m || !N->ext[target])
     return fail(EFM_EINVAL, "target %d is not an external metabolite", target);
@@ -354,6 +372,9 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
   std::vector<efm_level_stats> stats;
   efm::DevLevel L{};
   u64 *fa_keys, *fa_hash, *fb_keys, *fb_hash;
+  bool ordered = false;
+  uint32_t *sscore = nullptr;
+  std::vector<std::pair<int, int>> passes;   // (byte, refill) of the truncation's radix passes
 
   if (!ws) {
     HIPCHK(hipMalloc((void **)&ws, Lo.total));
@@ -388,6 +409,13 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
   L.depth_cap = D;
   L.debug_prime = (o.flags & EFM_OPT_EXACT_RANK) ? 1 : 0;
   L.no_gf2 = (o.flags & EFM_OPT_NO_GF2) ? 1 : 0;
+  ordered = hook && hook->orders();
+  if (ordered && !(o.flags & EFM_OPT_LEARNED)) {
+    rc = fail(EFM_EINVAL, "learned ordering needs the EFM_OPT_LEARNED workspace layout");
+    goto done;
+  }
+  sscore = ordered ? (uint32_t *)(ws + Lo.off_sscore) : nullptr;
+  L.sscore = sscore;
 
   HIPCHK(hipMemcpyAsync(ws + Lo.off_root, root.data(), Wt * 8, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(ws + Lo.off_sx, sx.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
@@ -474,10 +502,20 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
       sel_init.needed = o.frontier_cap;
       sel_init.nb = nsurv;
       HIPCHK(hipMemcpyAsync(L.selst, &sel_init, sizeof(sel_init), hipMemcpyHostToDevice, s));
-      const int top = (n - 1) / 8;
-      for (int byte = top, pass = 0; byte >= 0; --byte, ++pass) {
-        HIPCHK(efm::launch_select_hist(N->dn, L, byte, byte == top || (byte & 7) == 7, pass, s));
-        HIPCHK(efm::launch_select_split(N->dn, L, byte, pass, s));
+      // radix passes from the most significant byte: with a learned ordering the
+      // four bytes of the score word come first, then the key's bytes
+      passes.clear();
+      if (ordered) {
+        HIPCHK(hook->score(N, L, nsurv, sscore, s));
+        for (int b = 3; b >= 0; --b) passes.push_back({Wt * 8 + b, b == 3});
+      }
+      {
+        const int top = (n - 1) / 8;
+        for (int byte = top; byte >= 0; --byte) passes.push_back({byte, byte == top || (byte & 7) == 7});
+      }
+      for (size_t pass = 0; pass < passes.size(); ++pass) {
+        HIPCHK(efm::launch_select_hist(N->dn, L, passes[pass].first, passes[pass].second, (int)pass, s));
+        HIPCHK(efm::launch_select_split(N->dn, L, passes[pass].first, (int)pass, s));
       }
       if (timing) HIPCHK(hipEventRecord(ev[5], s));
     }
@@ -506,6 +544,10 @@ efm_status efm_enumerate(const efm_network *N, int32_t target, const efm_enum_op
       HIPCHK(hipEventElapsedTime(&t, ev[6], ev[7])); st.ms_materialize = t;
     }
     stats.push_back(st);
+    if (hook) {
+      const efm_status hr = hook->frontier(N, L.nkeys, L.nhash, Lo.fcap, st.kept, level, s);
+      if (hr != EFM_OK) { rc = hr; goto done; }
+    }
     nfound = std::min<int64_t>((int64_t)hc[efm::kFound], Lo.ecap);
     if (level > 0 && nparents > 0) branching = std::max(1.0, (double)st.children / (double)nparents);
     std::swap(fa_keys, fb_keys);
@@ -547,6 +589,8 @@ done:
   *out = R;
   return EFM_OK;
 }
+
+extern "C" {
 
 efm_status efm_result_info(const efm_result *res, int64_t *n_pathways, int32_t *words, uint32_t *status_flags,
                            int32_t *n_levels) {

@@ -51,6 +51,7 @@ enum FlagBits : u64 {
   kFlagFoundOverflow = 1ull << 9,
   kFlagIntOverflow = 1ull << 10,
   kFlagQueueOverflow = 1ull << 11,
+  kFlagFeatOverflow = 1ull << 12,
 };
 
 // Device tables of one network.  Masks are padded to the template widths
@@ -118,6 +119,7 @@ struct DevLevel {
   u64 *skey;              // [ucap] the key word the current selection byte lies in
   uint32_t *hist;         // [2][256], by pass parity
   SelState *selst;        // [2], by pass parity
+  const uint32_t *sscore; // [ucap] learned ordering: score word ranked before the key, or null
   u64 *counters;
   i128 *xscratch;         // exact kernel scratch: [xwaves][mi * kMaxDepth]
   int xwaves;

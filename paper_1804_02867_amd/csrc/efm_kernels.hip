@@ -523,7 +523,9 @@ __global__ __launch_bounds__(256) void select_hist_kernel(DevLevel L, int byte, 
     if (act) {
       u64 kw;
       if (refill) {
-        kw = key_word<W>(L, L.surv[i], byte >> 3);
+        // word W is the learned score word (ascending = higher score), ranked
+        // before every word of the key
+        kw = (byte >> 3) >= W ? (u64)L.sscore[i] : key_word<W>(L, L.surv[i], byte >> 3);
         L.skey[i] = kw;
       } else {
         kw = L.skey[i];

@@ -330,3 +330,12 @@ def graph_like(seed: int, m_int: int = 8, n_edges: int = 14, rev_p: float = 0.0)
     net = _net_from_columns(m_int, cols, [0] * len(cols), 2, f"graph{seed}")
     net.meta["edges"] = edges
     return net
+
+
+def learn_member(seed: int) -> Network:
+    """Network of the learned-ordering workload: the genome-scale generator
+    (power-law metabolite degrees, 30% reversible) at a tenth of its size, 40
+    internal metabolites, 60 reactions and 4 exchanges, small enough for the plain
+    traversal to finish exhaustively at depth cap 16."""
+    rng = np.random.default_rng(seed)
+    return powerlaw_network(rng, 40, 60, 4, 0.3, name=f"learn/{seed}")

@@ -49,13 +49,28 @@ def test_null_arguments_are_rejected(lib):
 
 
 def test_struct_layouts_match_the_header(tmp_path):
+    checks = [("efm_enum_opts", efm.EnumOpts, "stream"), ("efm_level_stats", efm.LevelStats, "ms_expand"),
+              ("efm_trace_opts", efm.TraceOpts, "seed"), ("efm_trace_info", efm.TraceInfo, "status"),
+              ("efm_train_opts", efm.TrainOpts, "stream"), ("efm_train_stats", efm.TrainStats, "ms"),
+              ("efm_batch_config", efm.BatchConfig, "networks_per_cu")]
+    body = "".join(f'printf("%zu %zu\\n", sizeof({c}), offsetof({c}, {f}));' for c, _, f in checks)
     src = tmp_path / "sz.c"
     src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "efm.h"\n'
-                   'int main(void){printf("%zu %zu %zu %zu\\n", sizeof(efm_enum_opts), '
-                   'offsetof(efm_enum_opts, stream), sizeof(efm_level_stats), '
-                   'offsetof(efm_level_stats, ms_expand));return 0;}\n')
+                   'int main(void){' + body + 'return 0;}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
-    assert got == [ctypes.sizeof(efm.EnumOpts), efm.EnumOpts.stream.offset,
-                   ctypes.sizeof(efm.LevelStats), efm.LevelStats.ms_expand.offset]
+    want = []
+    for _, cls, f in checks:
+        want += [ctypes.sizeof(cls), getattr(cls, f).offset]
+    assert got == want
+
+
+def test_header_constants_match_the_binding(tmp_path):
+    src = tmp_path / "k.c"
+    src.write_text('#include <stdio.h>\n#include "efm.h"\nint main(void){printf("%d %d %u %d\\n", '
+                   'EFM_FEAT_MAX, EFM_TRACE_WORDS, EFM_OPT_LEARNED, EFM_MAX_DEPTH);return 0;}\n')
+    exe = tmp_path / "k"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
+    assert got == [efm.FEAT_MAX, efm.TRACE_WORDS, efm.OPT_LEARNED, efm.MAX_DEPTH]
