@@ -25,6 +25,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# Modular multiply-reduce peak (mod 2^31-1), derived from the unit counts: 256 CUs x
+# 128 32-bit lanes per clock x 2.4 GHz = 78.6 T lane-ops/s, and 12 issue slots per
+# multiply-reduce (two quarter-rate 32-bit multiplies, four full-rate ops).
+MULMOD_PEAK_T = 256 * 128 * 2.4e9 / 12 / 1e12
+# HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs of one bench
+# step (calibrated on a 1 GiB device copy: FETCH_SIZE x 2, WRITE_SIZE x 1); None
+# when the kernel changed after the counters were taken.
+TRAFFIC_PER_LAUNCH = {"expand": 754.8e6, "rank": 172.0e6}
 
 
 def expand_bytes(level: dict, W: int) -> float:
@@ -193,6 +201,19 @@ def learned_section(args, efm, torch):
             "budgets": rows, "target_recall": 0.99}
 
 
+def copy_calibration(torch, nbytes=1 << 30, reps=4):
+    """Plain device-to-device copies of a known size: the reference that scales
+    the HBM byte counters of a profiled run."""
+    src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {reps} copies of {nbytes} bytes")
+    del src, dst
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -203,6 +224,10 @@ def main():
     ap.add_argument("--frontier-cap", type=int, default=1 << 20)
     ap.add_argument("--targets", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--sections", default="central,batch,learned",
+                    help="comma list of central, batch, learned (profiling runs pick one)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device to device 4 times (byte-counter reference)")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--batch-count", type=int, default=4096)
     ap.add_argument("--batch-depth-cap", type=int, default=12)
@@ -220,18 +245,40 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(see the sharding paragraph of the design notes)", file=sys.stderr)
         sys.exit(2)
+    sections = set(args.sections.split(","))
+    if args.no_batch:
+        sections.discard("batch")
+    if args.no_learned:
+        sections.discard("learned")
 
     batch_nets = None
-    if not args.no_batch:
+    if "batch" in sections:
         t = time.perf_counter()
         batch_nets = make_batch_networks(args.batch_count)
         log(f"batch: generated {len(batch_nets)} networks in {time.perf_counter() - t:.1f} s")
 
-    import numpy as np
     import torch
-    from paper_1804_02867_amd import efm, netgen
+    from paper_1804_02867_amd import efm
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        copy_calibration(torch)
+    line = {"metric": "balanced pathways/s + frontier items/s (HBM GB/s %peak); learned vs plain recall@speedup",
+            "value": None, "unit": "frontier items/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "u64", "data": "synthetic"}
+    if "central" in sections:
+        line.update(central_section(args, efm, torch))
+    if "batch" in sections:
+        line["batch"] = batch_sweep(args, batch_nets, efm, torch)
+    if "learned" in sections:
+        line["learned"] = learned_section(args, efm, torch)
+    print(json.dumps(line), flush=True)
+
+
+def central_section(args, efm, torch):
+    """The headline workload: every target of the central-shaped network."""
+    from paper_1804_02867_amd import netgen
     net = netgen.central(args.seed)
     S, rev, ext = net.arrays()
     W = (net.n + 63) // 64
@@ -271,6 +318,12 @@ def main():
     ms_total_kernels = {k: sum(lv[k] for rs in results for r in rs for lv in r.levels)
                         for k in ("ms_expand", "ms_rank", "ms_exact", "ms_select", "ms_materialize")}
     achieved = bytes_exp / (ms_exp * 1e-3) / 1e9 if ms_exp > 0 else 0.0
+    # rank stage (the dominant kernels): rows x k^2 modular multiplies per tested
+    # child of k reactions (children of loop level i have i + 2 reactions)
+    rank_ops = sum(lv["rank_rows"] * (i + 2) ** 2 for rs in results for r in rs for i, lv in enumerate(r.levels))
+    ms_rank = ms_total_kernels["ms_rank"]
+    achieved_rank = rank_ops / (ms_rank * 1e-3) / 1e12 if ms_rank > 0 else 0.0
+    shares = {k: v / max(sum(ms_total_kernels.values()), 1e-12) for k, v in ms_total_kernels.items()}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -289,7 +342,7 @@ def main():
                "sample": f"central seed {args.seed}, targets {sample_targets}, depth cap {args.depth_cap}, "
                          f"frontier cap {cap} (single-threaded oracle, {dt:.1f} s)"}
 
-    line = {
+    return {
         "metric": "balanced pathways/s + frontier items/s (HBM GB/s %peak); learned vs plain recall@speedup",
         "value": parents / elapsed,
         "unit": "frontier items/s",
@@ -310,17 +363,18 @@ def main():
         "children_per_s": children / elapsed,
         "pathways_per_step": pathways / args.steps,
         "kernel_ms_per_step": {k: v / args.steps for k, v in ms_total_kernels.items()},
-        "roofline": {"bound": "hbm", "kernel": "expand_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "launches": nlaunch, "avg_launch_ms": ms_exp / max(nlaunch, 1),
-                     "alg_bytes_per_launch": bytes_exp / max(nlaunch, 1)},
+        "kernel_share": shares,
+        "roofline": {"bound": "alu", "kernel": "rank stage (rank_parent_kernel + rank_kernel)",
+                     "achieved": achieved_rank, "peak": MULMOD_PEAK_T, "unit": "T mulmod/s",
+                     "frac": achieved_rank / MULMOD_PEAK_T, "traffic": TRAFFIC_PER_LAUNCH["rank"],
+                     "launches": nlaunch, "avg_launch_ms": ms_rank / max(nlaunch, 1),
+                     "alg_ops_per_launch": rank_ops / max(nlaunch, 1)},
+        "expand_roofline": {"bound": "hbm", "kernel": "expand_kernel", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC_PER_LAUNCH["expand"],
+                            "launches": nlaunch, "avg_launch_ms": ms_exp / max(nlaunch, 1),
+                            "alg_bytes_per_launch": bytes_exp / max(nlaunch, 1)},
         "cpu_baseline": cpu,
     }
-    if not args.no_batch:
-        line["batch"] = batch_sweep(args, batch_nets, efm, torch)
-    if not args.no_learned:
-        line["learned"] = learned_section(args, efm, torch)
-    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

@@ -101,6 +101,8 @@ typedef struct {
   double ms_exact;
   double ms_select;     /* truncation: scoring (learned ordering) and selection */
   double ms_materialize;
+  int64_t rank_rows;    /* sum over the row-closed children tested of the rows their test
+                           spans (the parent's touched internal metabolites) */
 } efm_level_stats;
 
 /* Create a network from S (Section 2.1).
@@ -225,7 +227,7 @@ typedef struct {
 } efm_trace_opts;
 
 typedef struct {
-  int64_t states;        /* frontier states seen (levels 2..) */
+  int64_t states;        /* frontier states seen */
   int64_t positives;     /* states contained in a pathway the plain run found (seen, not kept) */
   int64_t recorded;      /* records appended */
   int64_t pathways;      /* pathways the plain run found */
@@ -258,7 +260,8 @@ typedef struct {
  * efm_traces_info: records held and how many of them are positive.
  * efm_trace_collect (Section 4.1 traversal used as a teacher): runs the plain
  *   traversal of efm_enumerate with opts, then runs it again and, at every level
- *   from the second, labels each frontier state 1 when a pathway found by the
+ *   (the first frontier holds the target's producing reactions), labels each
+ *   frontier state 1 when a pathway found by the
  *   first run contains it, keeps the positives (a hashed sample of pos_max when
  *   there are more) and a hashed sample of the negatives (max(neg_min,
  *   neg_per_pos * kept positives) per level), and appends them.  EFM_EINVAL when

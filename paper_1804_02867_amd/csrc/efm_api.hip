@@ -534,6 +534,7 @@ efm_status enumerate_impl(const efm_network *N, int32_t target, const efm_enum_o
     st.independent = (int64_t)hc[efm::kIndep];
     st.emitted = (int64_t)hc[efm::kEmitted];
     st.kept = use_sel ? o.frontier_cap : nsurv;
+    st.rank_rows = (int64_t)hc[efm::kRankRows];
     if (timing) {
       float t;
       HIPCHK(hipEventElapsedTime(&t, ev[0], ev[1])); st.ms_expand = t;

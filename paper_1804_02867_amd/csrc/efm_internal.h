@@ -37,6 +37,7 @@ enum Counter {
   kCapped,         // independent children dropped by the depth cap
   kParQ,           // parents queued with their row-closed children
   kRowClosed,      // distinct row-closed children
+  kRankRows,       // sum over row-closed unpruned children of the rows their test spans
   kNumCounters
 };
 // Counters sit 256 bytes apart so that atomics on different counters never share

@@ -235,7 +235,7 @@ __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L
   const bool keep_indep = L.level + 1 < L.depth_cap;
   const int64_t nf = min((int64_t)L.nfound_prev, L.ecap);
   WaveBuf bsurv{stage[0][wib], 0}, bslow{stage[1][wib], 0};
-  u64 n_indep = 0, n_pruned = 0, n_capped = 0;
+  u64 n_indep = 0, n_pruned = 0, n_capped = 0, n_rows = 0;
 
   for (int64_t item = (int64_t)blockIdx.x * wpb + wib; item < nitems; item += (int64_t)gridDim.x * wpb) {
     const u64 p = L.parq[item];
@@ -277,12 +277,16 @@ __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L
       }
     }
     kall = 0;
+    int kp = 0, nch = 0;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
       A[w] = P[w] | M[w];                        // pruned children are gone from M
       kall += __popcll(A[w]);
+      kp += __popcll(P[w]);
+      nch += __popcll(M[w]);
     }
     bool full = kall <= 64 && !L.debug_prime && !L.no_gf2;
+    int rows = 0;            // rows the children's tests span: the parent's touched metabolites
     u64 rowm[MW];
     bool used[MW];
     int col = -1;
@@ -302,6 +306,7 @@ __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L
       for (int q = 0; q < MW; ++q) {
         // rows P does not touch are dropped (used) so they never serve as pivots
         const u64 T = wave_or(tm[q]);
+        rows += __popcll(T);
         rowm[q] = wave_transpose64(om[q]);
         used[q] = !((T >> lane) & 1ull);
       }
@@ -335,6 +340,14 @@ __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L
         }
       }
     }
+    if (!(kall <= 64 && !L.debug_prime && !L.no_gf2)) {
+      for (int c0 = 0; c0 < kp; c0 += 64) {
+        const int pc = c0 + lane < kp ? select_bit<W>(P, c0 + lane) : -1;
+#pragma unroll
+        for (int q = 0; q < MW; ++q) rows += __popcll(wave_or(pc >= 0 ? net.rxn_touchM[(int64_t)pc * MW + q] : 0ull));
+      }
+    }
+    n_rows += lane == 0 ? (u64)rows * (u64)nch : 0ull;
     // children, in reaction order: certified ones are independent
     u64 ccols = __ballot(child);
 #pragma unroll
@@ -364,9 +377,9 @@ __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L
   }
   wbuf_flush(bsurv, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
   wbuf_flush(bslow, L.rankq, &L.counters[cslot(kRankQ)], L.ucap, &L.counters[cslot(kFlags)]);
-  u64 v[3] = {n_indep, n_pruned, n_capped};
-  const int slots[3] = {kIndep, kPruned, kCapped};
-  block_counts<3>(v, L.counters, slots);
+  u64 v[4] = {n_indep, n_pruned, n_capped, n_rows};
+  const int slots[4] = {kIndep, kPruned, kCapped, kRankRows};
+  block_counts<4>(v, L.counters, slots);
 }
 
 // -------------------------------------------------------------------------- rank

@@ -48,7 +48,8 @@ class LevelStats(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in
                 ("parents", "children", "unique", "row_closed", "pruned", "independent", "emitted",
                  "kept")] + [(k, ctypes.c_double) for k in
-                             ("ms_expand", "ms_rank", "ms_exact", "ms_select", "ms_materialize")]
+                             ("ms_expand", "ms_rank", "ms_exact", "ms_select", "ms_materialize")] + [
+                    ("rank_rows", ctypes.c_int64)]
 
 
 class EfmError(RuntimeError):

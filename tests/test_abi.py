@@ -50,6 +50,7 @@ def test_null_arguments_are_rejected(lib):
 
 def test_struct_layouts_match_the_header(tmp_path):
     checks = [("efm_enum_opts", efm.EnumOpts, "stream"), ("efm_level_stats", efm.LevelStats, "ms_expand"),
+              ("efm_level_stats", efm.LevelStats, "rank_rows"),
               ("efm_trace_opts", efm.TraceOpts, "seed"), ("efm_trace_info", efm.TraceInfo, "status"),
               ("efm_train_opts", efm.TrainOpts, "stream"), ("efm_train_stats", efm.TrainStats, "ms"),
               ("efm_batch_config", efm.BatchConfig, "networks_per_cu")]
