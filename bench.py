@@ -36,10 +36,11 @@ TRAFFIC_PER_LAUNCH = {"expand": 754.8e6, "rank": 172.0e6}
 
 
 def expand_bytes(level: dict, W: int) -> float:
-    """Algorithmic HBM bytes of one expand launch: read every parent's key and
-    hash (8W + 8), one 8-byte table slot per generated child, one 8-byte reference
-    written per distinct child."""
-    return level["parents"] * (8 * W + 8) + level["children"] * 8 + level["unique"] * 8
+    """Algorithmic HBM bytes of one expand launch, per-unit figures of the step:
+    read every parent's key (8W bytes) and, per generated child, its key and an
+    8-byte hash slot (8W + 8 bytes).  (The kernel writes an 8-byte reference in
+    place of each child's key.)"""
+    return level["parents"] * (8 * W) + level["children"] * (8 * W + 8)
 
 
 def log(msg):

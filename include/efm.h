@@ -78,8 +78,8 @@ typedef struct {
                                     null-vector lift (slower; result unchanged) */
 #define EFM_OPT_NO_GF2 8u        /* skip the modulo-2 independence certificate, so every undecided
                                     rank test runs modulo the prime (result unchanged) */
-#define EFM_OPT_AUTOTUNE 16u     /* batch only: time candidate tile shapes once at creation and keep
-                                    the fastest */
+#define EFM_OPT_AUTOTUNE 16u     /* batch only: time candidate tile shapes once at creation (on every
+                                    4th network of the batch) and keep the fastest */
 #define EFM_OPT_TIME_KERNELS 4u  /* record HIP events around every kernel launch on the stream and
                                     report per-level kernel times in efm_level_stats */
 #define EFM_OPT_LEARNED 32u      /* workspace layout of efm_enumerate_learned (adds one 4-byte score

@@ -280,7 +280,7 @@ Layout make_layout(const efm_network *N, const efm_enum_opts *o) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o2 = off; off += align256(bytes); return o2; };
   L.off_counters = take(efm::kNumCounters * efm::kCounterStride * 8);
-  L.off_hist = take(2 * 256 * 4);
+  L.off_hist = take(3 * 256 * 4);
   L.off_selst = take(2 * sizeof(efm::SelState));
   L.off_root = take((size_t)Wt * 8);
   L.off_sx = take((size_t)N->n * 4);
@@ -497,7 +497,7 @@ efm_status enumerate_impl(const efm_network *N, int32_t target, const efm_enum_o
       use_sel = 1;
       status |= EFM_FRONTIER_TRUNCATED;
       HIPCHK(hipMemsetAsync(L.sel, 2, (size_t)nsurv, s));
-      HIPCHK(hipMemsetAsync(L.hist, 0, 2 * 256 * 4, s));
+      HIPCHK(hipMemsetAsync(L.hist, 0, 3 * 256 * 4, s));
       sel_init = efm::SelState{};
       sel_init.needed = o.frontier_cap;
       sel_init.nb = nsurv;
@@ -513,10 +513,13 @@ efm_status enumerate_impl(const efm_network *N, int32_t target, const efm_enum_o
         const int top = (n - 1) / 8;
         for (int byte = top; byte >= 0; --byte) passes.push_back({byte, byte == top || (byte & 7) == 7});
       }
-      for (size_t pass = 0; pass < passes.size(); ++pass) {
-        HIPCHK(efm::launch_select_hist(N->dn, L, passes[pass].first, passes[pass].second, (int)pass, s));
-        HIPCHK(efm::launch_select_split(N->dn, L, passes[pass].first, (int)pass, s));
-      }
+      // histogram of the first byte; then one sweep per further byte that applies
+      // the previous byte's decision and counts the next; the last decision alone
+      HIPCHK(efm::launch_select_hist(N->dn, L, passes[0].first, passes[0].second, 0, s));
+      for (size_t pass = 1; pass < passes.size(); ++pass)
+        HIPCHK(efm::launch_select_step(N->dn, L, passes[pass - 1].first, passes[pass].first, passes[pass].second,
+                                       (int)pass, s));
+      HIPCHK(efm::launch_select_split(N->dn, L, passes.back().first, (int)passes.size() - 1, s));
       if (timing) HIPCHK(hipEventRecord(ev[5], s));
     }
     if (timing) HIPCHK(hipEventRecord(ev[6], s));

@@ -484,6 +484,8 @@ using efm::u64;
 
 struct efm_batch {
   int count = 0, Wt = 0, MWt = 0, depth_cap = 0, dstride = 0;
+  int nsample = 0;                       // autotuner sample (every 4th network of the order)
+  const int32_t *sample_order = nullptr;
   std::vector<int> n_of, W_of;
   efm_batch_config cfg{};
   efm::BatchArgs args{};
@@ -640,6 +642,8 @@ efm_status efm_batch_create(const efm_network *const *nets, const int32_t *targe
     host.resize(host.size() + align256(sizeof(efm::BatchNet) * count));
     const size_t order_off = host.size();
     host.resize(host.size() + align256(sizeof(int32_t) * count));
+    const size_t sample_off = host.size();   // every 4th network of the order: the autotuner's sample
+    host.resize(host.size() + align256(sizeof(int32_t) * count));
     BCHK(hipMalloc(&b->blob, host.size()));
     char *dbase = (char *)b->blob;
     std::vector<efm::BatchNet> desc(count);
@@ -656,9 +660,14 @@ efm_status efm_batch_create(const efm_network *const *nets, const int32_t *targe
       return (int64_t)nets[a]->n * nets[a]->mi > (int64_t)nets[c]->n * nets[c]->mi;
     });
     memcpy(host.data() + order_off, order.data(), sizeof(int32_t) * count);
+    std::vector<int32_t> sample;
+    for (int i = 0; i < count; i += (count >= 256 ? 4 : 1)) sample.push_back(order[i]);
+    memcpy(host.data() + sample_off, sample.data(), sizeof(int32_t) * sample.size());
+    b->nsample = (int)sample.size();
     BCHK(hipMemcpy(b->blob, host.data(), host.size(), hipMemcpyHostToDevice));
     b->args.nets = (const efm::BatchNet *)(dbase + desc_off);
     b->args.order = (const int32_t *)(dbase + order_off);
+    b->sample_order = (const int32_t *)(dbase + sample_off);
   }
 
   {
@@ -705,19 +714,31 @@ efm_status efm_batch_create(const efm_network *const *nets, const int32_t *targe
   b->cfg.waves_per_network = 4;
   b->cfg.networks_per_cu = 4;
   if (o.flags & EFM_OPT_AUTOTUNE) {
+    // each candidate tile is timed once on a sample of the batch (every 4th
+    // network of the largest-first order, so the size mix is kept), after one
+    // warm-up launch
     const int cand[][2] = {{1, 8}, {2, 8}, {2, 4}, {4, 4}, {4, 2}, {8, 2}};
+    const efm::BatchArgs full = b->args;
+    const int full_count = b->count;
+    b->args.order = b->sample_order;
+    b->args.count = b->nsample;
+    b->count = b->nsample;
     float best = 1e30f;
     efm_batch_config best_cfg = b->cfg;
+    bool warm = false;
     for (auto &c : cand) {
       if (c[0] > max_waves(b)) continue;
       b->cfg.waves_per_network = c[0];
       b->cfg.networks_per_cu = c[1];
       if ((rc = capture(b)) != EFM_OK) goto bad;
       float ms = 0.f;
-      if ((rc = run_once(b, b->stream, nullptr)) != EFM_OK) goto bad;   // warm-up
+      if (!warm && (rc = run_once(b, b->stream, nullptr)) != EFM_OK) goto bad;
+      warm = true;
       if ((rc = run_once(b, b->stream, &ms)) != EFM_OK) goto bad;
       if (ms < best) { best = ms; best_cfg = b->cfg; }
     }
+    b->args = full;
+    b->count = full_count;
     b->cfg = best_cfg;
   }
   if ((rc = capture(b)) != EFM_OK) goto bad;

@@ -118,7 +118,7 @@ struct DevLevel {
   // truncation
   uint8_t *sel;           // [ucap] 0 rejected, 1 selected, 2 undecided
   u64 *skey;              // [ucap] the key word the current selection byte lies in
-  uint32_t *hist;         // [2][256], by pass parity
+  uint32_t *hist;         // [3][256], by pass % 3
   SelState *selst;        // [2], by pass parity
   const uint32_t *sscore; // [ucap] learned ordering: score word ranked before the key, or null
   u64 *counters;
@@ -138,6 +138,9 @@ hipError_t launch_materialize(const DevNet &net, const DevLevel &L, int use_sel,
 hipError_t launch_select_hist(const DevNet &net, const DevLevel &L, int byte, int refill, int pass,
                               hipStream_t s);
 hipError_t launch_select_split(const DevNet &net, const DevLevel &L, int byte, int pass, hipStream_t s);
+// pass-1's split and pass's histogram in one sweep (pass >= 1)
+hipError_t launch_select_step(const DevNet &net, const DevLevel &L, int prev_byte, int byte, int refill, int pass,
+                              hipStream_t s);
 hipError_t launch_clear(u64 *p, size_t n, hipStream_t s);
 
 }  // namespace efm

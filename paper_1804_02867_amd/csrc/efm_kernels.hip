@@ -520,7 +520,7 @@ __global__ __launch_bounds__(256) void select_hist_kernel(DevLevel L, int byte, 
   __shared__ uint32_t h[256];
   const SelState *st = L.selst + (pass & 1);
   if (st->done) return;
-  uint32_t *hist = L.hist + 256 * (pass & 1);
+  uint32_t *hist = L.hist + 256 * (pass % 3);
   const int64_t n = min((int64_t)L.counters[cslot(kSurv)], L.ucap);
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -567,9 +567,9 @@ __global__ __launch_bounds__(256) void select_split_kernel(DevLevel L, int byte,
   __shared__ int64_t rem;
   const SelState *st = L.selst + (pass & 1);
   SelState *nx = L.selst + ((pass + 1) & 1);
-  const uint32_t *hist = L.hist + 256 * (pass & 1);
+  const uint32_t *hist = L.hist + 256 * (pass % 3);
   const bool lead = blockIdx.x == 0;
-  if (lead) L.hist[256 * ((pass + 1) & 1) + threadIdx.x] = 0;
+  if (lead) L.hist[256 * ((pass + 1) % 3) + threadIdx.x] = 0;
   if (st->done) {
     if (lead && threadIdx.x == 0) *nx = *st;
     return;
@@ -611,6 +611,91 @@ __global__ __launch_bounds__(256) void select_split_kernel(DevLevel L, int byte,
     if (d < digit || (d == digit && all_sel)) L.sel[i] = 1;
     else if (d > digit) L.sel[i] = 0;
   }
+}
+
+// One pass of the selection in one sweep: applies pass-1's decision (from its
+// finished histogram, derived by every block as in select_split_kernel) and adds
+// the digits of `byte` of the members still undecided to pass's histogram.
+// Histograms are triple-buffered (pass % 3): block 0 clears the one for pass+1,
+// which nobody reads or writes during this launch.
+template <int W>
+__global__ __launch_bounds__(256) void select_step_kernel(DevLevel L, int prev_byte, int byte, int refill, int pass) {
+  __shared__ uint32_t dec[3];
+  __shared__ int64_t rem;
+  __shared__ uint32_t h[256];
+  const SelState *st = L.selst + ((pass - 1) & 1);
+  SelState *nx = L.selst + (pass & 1);
+  const uint32_t *hprev = L.hist + 256 * ((pass - 1) % 3);
+  uint32_t *hcur = L.hist + 256 * (pass % 3);
+  const bool lead = blockIdx.x == 0;
+  if (lead) L.hist[256 * ((pass + 1) % 3) + threadIdx.x] = 0;
+  if (st->done) {
+    if (lead && threadIdx.x == 0) *nx = *st;
+    return;
+  }
+  h[threadIdx.x] = 0;
+  if (threadIdx.x == 0) {
+    int64_t cum = 0;
+    int v = 0;
+    for (v = 0; v < 255; ++v) {
+      if (cum + (int64_t)hprev[v] >= st->needed) break;
+      cum += hprev[v];
+    }
+    const int64_t hv = hprev[v];
+    const int64_t remaining = st->needed - cum;
+    const uint32_t all_sel = hv == remaining ? 1u : 0u;
+    dec[0] = (uint32_t)v;
+    dec[1] = all_sel;
+    dec[2] = (!all_sel && hv == st->nb) ? 1u : 0u;
+    rem = remaining;
+    if (lead) {
+      SelState t = *st;
+      if (!dec[2]) {
+        t.needed = remaining;
+        t.nb = hv;
+        t.done = all_sel;
+      }
+      *nx = t;
+    }
+  }
+  __syncthreads();
+  const bool decides = !dec[2];
+  const uint32_t digit = dec[0];
+  const bool all_sel = dec[1] != 0;
+  const int pshift = (prev_byte & 7) * 8, shift = (byte & 7) * 8;
+  const int lane = lane_id();
+  const int64_t n = min((int64_t)L.counters[cslot(kSurv)], L.ucap);
+  const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
+    const int64_t i = base + lane;
+    bool act = i < n && L.sel[i] == 2;
+    uint32_t d = 0;
+    if (act) {
+      u64 kw = L.skey[i];
+      if (decides) {
+        const uint32_t dp = (uint32_t)((kw >> pshift) & 0xFF);
+        if (dp < digit || (dp == digit && all_sel)) { L.sel[i] = 1; act = false; }
+        else if (dp > digit) { L.sel[i] = 0; act = false; }
+      }
+      if (act) {
+        if (refill) {
+          kw = (byte >> 3) >= W ? (u64)L.sscore[i] : key_word<W>(L, L.surv[i], byte >> 3);
+          L.skey[i] = kw;
+        }
+        d = (uint32_t)((kw >> shift) & 0xFF);
+      }
+    }
+    u64 pending = __ballot(act);
+    while (pending) {
+      const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)d, __ffsll((long long)pending) - 1);
+      const u64 m = __ballot(act && d == v) & pending;
+      if (lane == __ffsll((long long)m) - 1) atomicAdd(&h[v], (uint32_t)__popcll(m));
+      pending &= ~m;
+    }
+  }
+  __syncthreads();
+  if (h[threadIdx.x]) atomicAdd(&hcur[threadIdx.x], h[threadIdx.x]);
 }
 
 // Writes the next frontier.  Without a cap the survivor order is kept (position =
@@ -781,6 +866,17 @@ static void do_split(const DevLevel &L, int byte, int pass, hipStream_t s) {
 }
 hipError_t launch_select_split(const DevNet &net, const DevLevel &L, int byte, int pass, hipStream_t s) {
   EFM_DISPATCH_W(net.Wt, do_split, L, byte, pass, s);
+  return hipGetLastError();
+}
+
+template <int W>
+static void do_step(const DevLevel &L, int prev_byte, int byte, int refill, int pass, hipStream_t s) {
+  hipLaunchKernelGGL((select_step_kernel<W>), dim3((unsigned)(num_cus() * 4)), dim3(256), 0, s, L, prev_byte, byte,
+                     refill, pass);
+}
+hipError_t launch_select_step(const DevNet &net, const DevLevel &L, int prev_byte, int byte, int refill, int pass,
+                              hipStream_t s) {
+  EFM_DISPATCH_W(net.Wt, do_step, L, prev_byte, byte, refill, pass, s);
   return hipGetLastError();
 }
 
