@@ -85,6 +85,13 @@ DEVI void block_counts(u64 (&v)[NC], u64 *counters, const int (&slot)[NC]) {
   if (threadIdx.x < NC && acc[threadIdx.x]) atomicAdd(&counters[cslot(slot[threadIdx.x])], acc[threadIdx.x]);
 }
 
+// 64-bit value of lane src, broadcast to the wave
+DEVI u64 readlane64(u64 v, int src) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
+  return ((u64)hi << 32) | lo;
+}
+
 DEVI int wave_max_int(int v) {
   for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
   return v;

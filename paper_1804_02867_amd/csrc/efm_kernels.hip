@@ -228,6 +228,7 @@ __global__ __launch_bounds__(256) void expand_kernel(DevNet net, DevLevel L) {
 template <int W, int MW>
 __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L, int prune) {
   __shared__ u64 stage[2][4][kWaveBuf];
+  __shared__ uint16_t colx[4][64];
   const int wib = threadIdx.x >> 6;
   const int lane = lane_id();
   const int wpb = blockDim.x >> 6;
@@ -285,95 +286,95 @@ __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L
       kp += __popcll(P[w]);
       nch += __popcll(M[w]);
     }
-    bool full = kall <= 64 && !L.debug_prime && !L.no_gf2;
+    const bool full = kall <= 64 && !L.debug_prime && !L.no_gf2;
     int rows = 0;            // rows the children's tests span: the parent's touched metabolites
-    u64 rowm[MW];
-    bool used[MW];
-    int col = -1;
-    bool child = false;
     if (full) {
-      col = lane < kall ? select_bit<W>(A, lane) : -1;
+      // one column per lane, in reaction order: lane j holds the j-th reaction of
+      // P | children (compacted through LDS), as its odd-coefficient mask over the
+      // internal metabolites (S mod 2)
+      {
+        int base = 0;
+#pragma unroll
+        for (int w = 0; w < W; ++w) {
+          if ((A[w] >> lane) & 1ull) colx[wib][base + __popcll(A[w] & lanes_below(lane))] = (uint16_t)(w * 64 + lane);
+          base += __popcll(A[w]);
+        }
+      }
+      __threadfence_block();
+      const int col = lane < kall ? (int)colx[wib][lane] : -1;
+      bool child = false;
 #pragma unroll
       for (int w = 0; w < W; ++w)
         if (col >= 0 && (col >> 6) == w) child = (M[w] >> (col & 63)) & 1ull;
-      u64 om[MW], tm[MW];
+      u64 v[MW];
 #pragma unroll
       for (int q = 0; q < MW; ++q) {
-        om[q] = col >= 0 ? net.rxn_oddM[(int64_t)col * MW + q] : 0ull;
-        tm[q] = (col >= 0 && !child) ? net.rxn_touchM[(int64_t)col * MW + q] : 0ull;
+        v[q] = col >= 0 ? net.rxn_oddM[(int64_t)col * MW + q] : 0ull;
+        rows += __popcll(wave_or((col >= 0 && !child) ? net.rxn_touchM[(int64_t)col * MW + q] : 0ull));
       }
-#pragma unroll
-      for (int q = 0; q < MW; ++q) {
-        // rows P does not touch are dropped (used) so they never serve as pivots
-        const u64 T = wave_or(tm[q]);
-        rows += __popcll(T);
-        rowm[q] = wave_transpose64(om[q]);
-        used[q] = !((T >> lane) & 1ull);
-      }
-      u64 cols = __ballot(col >= 0 && !child);
-      while (cols) {
-        const int c = __ffsll((long long)cols) - 1;
-        cols &= cols - 1;
-        int pq = -1, pl = -1;
+      // column elimination modulo 2 by the parent's columns, in order: each reduced
+      // parent column gives a pivot row (its lowest set bit) that is cleared from
+      // every other column; pivots of later columns never set an earlier pivot row
+      u64 pcols = __ballot(col >= 0 && !child);
+      bool ok = true;
+      while (pcols) {
+        const int j = __ffsll((long long)pcols) - 1;
+        pcols &= pcols - 1;
+        u64 pv[MW];
+        int pq = -1;
 #pragma unroll
         for (int q = 0; q < MW; ++q) {
-          if (pq < 0) {
-            const u64 cand = __ballot(!used[q] && ((rowm[q] >> c) & 1ull));
-            if (cand) { pq = q; pl = __ffsll((long long)cand) - 1; }
-          }
+          pv[q] = readlane64(v[q], j);
+          if (pq < 0 && pv[q] != 0) pq = q;
         }
-        if (pq < 0) { full = false; break; }
-        u64 prow = 0;
+        if (pq < 0) { ok = false; break; }    // the parent is dependent modulo 2: no certificate
+        int b = 0;
+        u64 vq = 0;
 #pragma unroll
-        for (int q = 0; q < MW; ++q) {
-          if (q == pq) {
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)rowm[q], pl);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(rowm[q] >> 32), pl);
-            prow = ((u64)hi << 32) | lo;
-          }
-        }
+        for (int q = 0; q < MW; ++q)
+          if (q == pq) { b = __builtin_ctzll(pv[q]); vq = v[q]; }
+        if (lane != j && ((vq >> b) & 1ull)) {
 #pragma unroll
-        for (int q = 0; q < MW; ++q) {
-          const bool me = (q == pq) && (lane == pl);
-          if (!me && ((rowm[q] >> c) & 1ull)) rowm[q] ^= prow;
-          if (me) used[q] = true;
+          for (int q = 0; q < MW; ++q) v[q] ^= pv[q];
         }
       }
-    }
-    if (!(kall <= 64 && !L.debug_prime && !L.no_gf2)) {
+      // a child whose reduced column is nonzero is outside the parent's span
+      // modulo 2, hence independent over the rationals
+      bool nz = false;
+#pragma unroll
+      for (int q = 0; q < MW; ++q) nz = nz || v[q] != 0;
+      const bool cert = ok && child && nz;
+      const u64 ref = ((u64)p << 12) | ((u64)(col < 0 ? 0 : col) << 1) | 1ull;
+      const u64 cm = __ballot(cert);
+      if (lane == 0) {
+        n_indep += __popcll(cm);
+        n_capped += keep_indep ? 0 : __popcll(cm);
+      }
+      wbuf_push(bsurv, cert && keep_indep, ref, L.surv, &L.counters[cslot(kSurv)], L.ucap,
+                &L.counters[cslot(kFlags)]);
+      wbuf_push(bslow, child && !cert, ref, L.rankq, &L.counters[cslot(kRankQ)], L.ucap,
+                &L.counters[cslot(kFlags)]);
+      __threadfence_block();
+    } else {
+      // no certificate (too many columns, or disabled): every child is tested
       for (int c0 = 0; c0 < kp; c0 += 64) {
         const int pc = c0 + lane < kp ? select_bit<W>(P, c0 + lane) : -1;
 #pragma unroll
         for (int q = 0; q < MW; ++q) rows += __popcll(wave_or(pc >= 0 ? net.rxn_touchM[(int64_t)pc * MW + q] : 0ull));
       }
-    }
-    n_rows += lane == 0 ? (u64)rows * (u64)nch : 0ull;
-    // children, in reaction order: certified ones are independent
-    u64 ccols = __ballot(child);
 #pragma unroll
-    for (int w = 0; w < W; ++w) {
-      u64 bits = M[w];
-      while (bits) {
-        const int r = w * 64 + __builtin_ctzll(bits);
-        bits &= bits - 1;
-        bool cert = false;
-        if (full) {
-          const int c = __ffsll((long long)ccols) - 1;   // children's columns come in reaction order
-          ccols &= ccols - 1;
-          bool any = false;
-#pragma unroll
-          for (int q = 0; q < MW; ++q) any = any || (!used[q] && ((rowm[q] >> c) & 1ull));
-          cert = __ballot(any) != 0;
+      for (int w = 0; w < W; ++w) {
+        u64 bits = M[w];
+        while (bits) {
+          const int r = w * 64 + __builtin_ctzll(bits);
+          bits &= bits - 1;
+          const u64 ref = (p << 12) | ((u64)r << 1) | 1ull;
+          wbuf_push(bslow, lane == 0, ref, L.rankq, &L.counters[cslot(kRankQ)], L.ucap,
+                    &L.counters[cslot(kFlags)]);
         }
-        const u64 ref = (p << 12) | ((u64)r << 1) | 1ull;
-        n_indep += (cert && lane == 0) ? 1 : 0;
-        n_capped += (cert && !keep_indep && lane == 0) ? 1 : 0;
-        wbuf_push(bsurv, cert && keep_indep && lane == 0, ref, L.surv, &L.counters[cslot(kSurv)], L.ucap,
-                  &L.counters[cslot(kFlags)]);
-        wbuf_push(bslow, !cert && lane == 0, ref, L.rankq, &L.counters[cslot(kRankQ)], L.ucap,
-                  &L.counters[cslot(kFlags)]);
       }
     }
+    n_rows += lane == 0 ? (u64)rows * (u64)nch : 0ull;
   }
   wbuf_flush(bsurv, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
   wbuf_flush(bslow, L.rankq, &L.counters[cslot(kRankQ)], L.ucap, &L.counters[cslot(kFlags)]);

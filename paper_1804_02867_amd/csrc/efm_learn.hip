@@ -90,12 +90,6 @@ DEVI u64 mix64(u64 x) {
   return x ^ (x >> 31);
 }
 
-DEVI u64 readlane64(u64 v, int src) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, src);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), src);
-  return ((u64)hi << 32) | lo;
-}
-
 // Model input of the partial pathway K (the same in every lane) as entry words in
 // lst (wave-private LDS): its reactions in increasing index (wave ballot over
 // the bits of each key word), then the internal metabolites with a non-zero
