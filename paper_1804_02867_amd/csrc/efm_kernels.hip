@@ -218,27 +218,23 @@ __global__ __launch_bounds__(256) void expand_kernel(DevNet net, DevLevel L) {
 
 // ------------------------------------------------------------------- rank (parent)
 // One wave per parent P with its distinct row-closed children r_1..r_m.  Every
-// child's rows lie inside P's rows.  Lane j holds column j of P | {r_1..r_m}.
-// The rows are bit masks over those columns (odd coefficients); XOR elimination
-// over P's columns only, applied to whole rows, leaves each child's column
-// reduced against P modulo 2, so a child is certified independent exactly when
-// its reduced column has a 1 in a row P did not use as a pivot.  Independence
-// modulo 2 implies independence over the rationals.  Children not certified
-// (or pruned by the found set) go on to the per-child test.
-template <int W, int MW>
-__global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L, int prune) {
-  __shared__ u64 stage[2][4][kWaveBuf];
-  __shared__ uint16_t colx[4][64];
-  const int wib = threadIdx.x >> 6;
-  const int lane = lane_id();
-  const int wpb = blockDim.x >> 6;
-  const int64_t nitems = min((int64_t)L.counters[cslot(kParQ)], L.ucap);
-  const bool keep_indep = L.level + 1 < L.depth_cap;
-  const int64_t nf = min((int64_t)L.nfound_prev, L.ecap);
-  WaveBuf bsurv{stage[0][wib], 0}, bslow{stage[1][wib], 0};
-  u64 n_indep = 0, n_pruned = 0, n_capped = 0, n_rows = 0;
+// child's rows lie inside P's rows.  Lane j holds column j of P | {r_1..r_m} (in
+// reaction order) as the mask of its odd coefficients over the internal
+// metabolites; column elimination modulo 2 by P's columns leaves each child's
+// column reduced against P, so a child is certified independent exactly when its
+// reduced column is nonzero.  Independence modulo 2 implies independence over the
+// rationals.  Children not certified (or pruned by the found set) go on to the
+// per-child test.  Two parents of at most 32 columns each share one wave, one per
+// half.
+struct RankCounts {
+  u64 indep = 0, pruned = 0, capped = 0, rows = 0;
+};
 
-  for (int64_t item = (int64_t)blockIdx.x * wpb + wib; item < nitems; item += (int64_t)gridDim.x * wpb) {
+template <int W, int MW>
+DEVI void rank_parent_one(const DevNet &net, const DevLevel &L, int64_t item, int prune, int64_t nf,
+                          bool keep_indep, uint16_t *colx, WaveBuf &bsurv, WaveBuf &bslow, RankCounts &cnt) {
+  const int lane = lane_id();
+  u64 &n_indep = cnt.indep, &n_pruned = cnt.pruned, &n_capped = cnt.capped, &n_rows = cnt.rows;
     const u64 p = L.parq[item];
     u64 P[W], M[W], A[W];
     int kall = 0;
@@ -296,12 +292,12 @@ __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L
         int base = 0;
 #pragma unroll
         for (int w = 0; w < W; ++w) {
-          if ((A[w] >> lane) & 1ull) colx[wib][base + __popcll(A[w] & lanes_below(lane))] = (uint16_t)(w * 64 + lane);
+          if ((A[w] >> lane) & 1ull) colx[base + __popcll(A[w] & lanes_below(lane))] = (uint16_t)(w * 64 + lane);
           base += __popcll(A[w]);
         }
       }
       __threadfence_block();
-      const int col = lane < kall ? (int)colx[wib][lane] : -1;
+      const int col = lane < kall ? (int)colx[lane] : -1;
       bool child = false;
 #pragma unroll
       for (int w = 0; w < W; ++w)
@@ -375,10 +371,138 @@ __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L
       }
     }
     n_rows += lane == 0 ? (u64)rows * (u64)nch : 0ull;
+}
+
+// two parents, one per half-wave (both of at most 32 columns, no found-set prune)
+template <int W, int MW>
+DEVI void rank_parent_two(const DevNet &net, const DevLevel &L, int64_t i0, int64_t i1, bool keep_indep,
+                          uint16_t *colx, WaveBuf &bsurv, WaveBuf &bslow, RankCounts &cnt) {
+  const int lane = lane_id();
+  const int h = lane >> 5, hl = lane & 31;
+  const int64_t item = h ? i1 : i0;
+  const u64 p = L.parq[item];
+  u64 P[W], M[W], A[W];
+  int kall = 0, nch = 0;
+#pragma unroll
+  for (int w = 0; w < W; ++w) {
+    P[w] = L.keys[(int64_t)w * L.fcap + p];
+    M[w] = L.parmask[item * W + w];
+    A[w] = P[w] | M[w];
+    kall += __popcll(A[w]);
+    nch += __popcll(M[w]);
+  }
+  // columns of this half's parent, in reaction order, into colx[32h ..]
+  {
+    int base = 0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+#pragma unroll
+      for (int sub = 0; sub < 2; ++sub) {
+        const int b = hl + 32 * sub;
+        if ((A[w] >> b) & 1ull) colx[32 * h + base + __popcll(A[w] & ((1ull << b) - 1ull))] = (uint16_t)(w * 64 + b);
+      }
+      base += __popcll(A[w]);
+    }
+  }
+  __threadfence_block();
+  const int col = hl < kall ? (int)colx[32 * h + hl] : -1;
+  bool child = false;
+#pragma unroll
+  for (int w = 0; w < W; ++w)
+    if (col >= 0 && (col >> 6) == w) child = (M[w] >> (col & 63)) & 1ull;
+  u64 v[MW];
+  int rows = 0;
+#pragma unroll
+  for (int q = 0; q < MW; ++q) {
+    v[q] = col >= 0 ? net.rxn_oddM[(int64_t)col * MW + q] : 0ull;
+    u64 t = (col >= 0 && !child) ? net.rxn_touchM[(int64_t)col * MW + q] : 0ull;
+    for (int off = 16; off > 0; off >>= 1) t |= __shfl_xor(t, off);     // OR within the half
+    rows += __popcll(t);
+  }
+  const u64 pc = __ballot(col >= 0 && !child);
+  u64 pa = pc & 0xFFFFFFFFull, pb = pc >> 32;
+  bool ok = true;
+  while (pa | pb) {
+    const int ja = pa ? __ffsll((long long)pa) - 1 : -1;
+    const int jb = pb ? 32 + __ffsll((long long)pb) - 1 : -1;
+    if (pa) pa &= pa - 1;
+    if (pb) pb &= pb - 1;
+    const int j = h ? jb : ja;
+    const int src = j >= 0 ? j : lane;
+    u64 pv[MW];
+    int pq = -1;
+#pragma unroll
+    for (int q = 0; q < MW; ++q) {
+      const uint32_t lo = (uint32_t)__shfl((int)(uint32_t)v[q], src);
+      const uint32_t hi = (uint32_t)__shfl((int)(uint32_t)(v[q] >> 32), src);
+      pv[q] = ((u64)hi << 32) | lo;
+      if (pq < 0 && pv[q] != 0) pq = q;
+    }
+    if (j < 0 || !ok) continue;               // this half is done (or has no certificate)
+    if (pq < 0) { ok = false; continue; }     // its parent is dependent modulo 2
+    int b = 0;
+    u64 vq = 0;
+#pragma unroll
+    for (int q = 0; q < MW; ++q)
+      if (q == pq) { b = __builtin_ctzll(pv[q]); vq = v[q]; }
+    if (lane != j && ((vq >> b) & 1ull)) {
+#pragma unroll
+      for (int q = 0; q < MW; ++q) v[q] ^= pv[q];
+    }
+  }
+  bool nz = false;
+#pragma unroll
+  for (int q = 0; q < MW; ++q) nz = nz || v[q] != 0;
+  const bool cert = ok && child && nz;
+  const u64 ref = (p << 12) | ((u64)(col < 0 ? 0 : col) << 1) | 1ull;
+  const u64 cm = __ballot(cert);
+  if (lane == 0) {
+    cnt.indep += __popcll(cm);
+    cnt.capped += keep_indep ? 0 : __popcll(cm);
+  }
+  if (hl == 0) cnt.rows += (u64)rows * (u64)nch;
+  wbuf_push(bsurv, cert && keep_indep, ref, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
+  wbuf_push(bslow, child && !cert, ref, L.rankq, &L.counters[cslot(kRankQ)], L.ucap, &L.counters[cslot(kFlags)]);
+  __threadfence_block();
+}
+
+template <int W, int MW>
+__global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L, int prune) {
+  __shared__ u64 stage[2][4][kWaveBuf];
+  __shared__ uint16_t colx[4][64];
+  const int wib = threadIdx.x >> 6;
+  const int wpb = blockDim.x >> 6;
+  const int64_t nitems = min((int64_t)L.counters[cslot(kParQ)], L.ucap);
+  const bool keep_indep = L.level + 1 < L.depth_cap;
+  const int64_t nf = min((int64_t)L.nfound_prev, L.ecap);
+  const bool pairs_ok = !(prune && nf > 0) && !L.debug_prime && !L.no_gf2;
+  WaveBuf bsurv{stage[0][wib], 0}, bslow{stage[1][wib], 0};
+  RankCounts cnt;
+
+  // items in pairs: two narrow parents share the wave, otherwise one at a time
+  for (int64_t pr = (int64_t)blockIdx.x * wpb + wib; 2 * pr < nitems; pr += (int64_t)gridDim.x * wpb) {
+    const int64_t i0 = 2 * pr, i1 = i0 + 1;
+    bool two = pairs_ok && i1 < nitems;
+    if (two) {
+      int k0 = 0, k1 = 0;
+      const u64 p0 = L.parq[i0], p1 = L.parq[i1];
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        k0 += __popcll(L.keys[(int64_t)w * L.fcap + p0] | L.parmask[i0 * W + w]);
+        k1 += __popcll(L.keys[(int64_t)w * L.fcap + p1] | L.parmask[i1 * W + w]);
+      }
+      two = k0 <= 32 && k1 <= 32;
+    }
+    if (two) {
+      rank_parent_two<W, MW>(net, L, i0, i1, keep_indep, colx[wib], bsurv, bslow, cnt);
+    } else {
+      rank_parent_one<W, MW>(net, L, i0, prune, nf, keep_indep, colx[wib], bsurv, bslow, cnt);
+      if (i1 < nitems) rank_parent_one<W, MW>(net, L, i1, prune, nf, keep_indep, colx[wib], bsurv, bslow, cnt);
+    }
   }
   wbuf_flush(bsurv, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
   wbuf_flush(bslow, L.rankq, &L.counters[cslot(kRankQ)], L.ucap, &L.counters[cslot(kFlags)]);
-  u64 v[4] = {n_indep, n_pruned, n_capped, n_rows};
+  u64 v[4] = {cnt.indep, cnt.pruned, cnt.capped, cnt.rows};
   const int slots[4] = {kIndep, kPruned, kCapped, kRankRows};
   block_counts<4>(v, L.counters, slots);
 }
