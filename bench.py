@@ -243,8 +243,8 @@ def main():
     ap.add_argument("--learned-budgets", default="14,16,18,20,22")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see the sharding paragraph of the design notes)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the traversal would shard children by hash over GPUs; not implemented)", file=sys.stderr)
         sys.exit(2)
     sections = set(args.sections.split(","))
     if args.no_batch:
