@@ -226,7 +226,7 @@ def main():
     ap.add_argument("--targets", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sections", default="central,batch,learned",
-                    help="comma list of central, batch, learned (profiling runs pick one)")
+                    help="comma list of central, batch, learned, genome (profiling runs pick one)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device to device 4 times (byte-counter reference)")
     ap.add_argument("--no-batch", action="store_true")
@@ -274,7 +274,33 @@ def main():
         line["batch"] = batch_sweep(args, batch_nets, efm, torch)
     if "learned" in sections:
         line["learned"] = learned_section(args, efm, torch)
+    if "genome" in sections:
+        line["genome"] = genome_section(args, efm, torch)
     print(json.dumps(line), flush=True)
+
+
+def genome_section(args, efm, torch):
+    """The genome-shaped network at its full caps (depth 40, frontier 2^26), once."""
+    from paper_1804_02867_amd import netgen
+    net = netgen.genome(args.seed)
+    g = efm.Network(*net.arrays())
+    kw = dict(depth_cap=40, frontier_cap=1 << 26, unique_cap=1 << 30, found_cap=1 << 16, flags=efm.OPT_TIME_KERNELS)
+    ws = torch.empty(efm.workspace_bytes(g, efm.make_opts(**kw)), dtype=torch.uint8, device="cuda")
+    log(f"genome: workspace {ws.numel() / 2**30:.1f} GiB")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    r = efm.enumerate_pathways(g, net.targets[0], workspace=ws, **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    parents = sum(lv["parents"] for lv in r.levels)
+    children = sum(lv["children"] for lv in r.levels)
+    log(f"genome: {parents} parents in {dt:.1f} s")
+    return {"workload": f"genome-shaped 400x640 network seed {args.seed}, target {net.targets[0]}, depth cap 40, "
+                        f"frontier cap 2^26", "s": dt, "frontier_items_per_s": parents / dt,
+            "children_per_s": children / dt, "pathways": int(r.count), "status": int(r.status),
+            "workspace_gib": ws.numel() / 2**30,
+            "kernel_ms": {k: sum(lv[k] for lv in r.levels)
+                          for k in ("ms_expand", "ms_rank", "ms_exact", "ms_select", "ms_materialize")}}
 
 
 def central_section(args, efm, torch):

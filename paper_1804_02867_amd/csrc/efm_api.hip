@@ -291,8 +291,8 @@ Layout make_layout(const efm_network *N, const efm_enum_opts *o) {
   L.off_table = take((size_t)L.tcap * 8);
   L.off_surv = take((size_t)L.ucap * 8);
   L.off_rankq = take((size_t)L.ucap * 8);
-  L.off_parq = take((size_t)L.ucap * 8);
-  L.off_parmask = take((size_t)L.ucap * Wt * 8);
+  L.off_parq = take((size_t)L.fcap * 8);            // parents with row-closed children
+  L.off_parmask = take((size_t)L.fcap * Wt * 8);
   L.off_exactq = take((size_t)L.ucap * 8);
   L.off_sel = take((size_t)L.ucap);
   L.off_skey = take((size_t)L.ucap * 8);

@@ -101,8 +101,8 @@ struct DevLevel {
   int tag;                // 1..127, distinct for every expand launch since the last clear
   u64 *surv;              // [ucap] refs of independent children
   u64 *rankq;             // [ucap] refs of row-closed children left undecided per parent
-  u64 *parq;              // [ucap] parents with distinct row-closed children
-  u64 *parmask;           // [ucap][Wt] those children, as a reaction mask
+  u64 *parq;              // [fcap] parents with distinct row-closed children
+  u64 *parmask;           // [fcap][Wt] those children, as a reaction mask
   u64 *exactq;            // [ucap] refs needing exact arithmetic
   int64_t ucap;
   // next frontier

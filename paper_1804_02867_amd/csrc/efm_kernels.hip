@@ -201,7 +201,7 @@ __global__ __launch_bounds__(256) void expand_kernel(DevNet net, DevLevel L) {
       b0 = __shfl(b0, leader);
       if (any) {
         const u64 idx = b0 + (u64)__popcll(m & lanes_below(lane_id()));
-        if ((int64_t)idx < L.ucap) {
+        if ((int64_t)idx < L.fcap) {           // one entry per parent: at most the frontier capacity
           L.parq[idx] = (u64)p;
 #pragma unroll
           for (int w = 0; w < W; ++w) L.parmask[(int64_t)idx * W + w] = rcm[w];
@@ -472,7 +472,7 @@ __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L
   __shared__ uint16_t colx[4][64];
   const int wib = threadIdx.x >> 6;
   const int wpb = blockDim.x >> 6;
-  const int64_t nitems = min((int64_t)L.counters[cslot(kParQ)], L.ucap);
+  const int64_t nitems = min((int64_t)L.counters[cslot(kParQ)], L.fcap);
   const bool keep_indep = L.level + 1 < L.depth_cap;
   const int64_t nf = min((int64_t)L.nfound_prev, L.ecap);
   const bool pairs_ok = !(prune && nf > 0) && !L.debug_prime && !L.no_gf2;
