@@ -91,6 +91,7 @@ def batch_sweep(args, nets, efm, torch):
            "ms_per_sweep": dt * 1e3, "networks_per_s": len(nets) / dt, "pathways_per_s": pathways / dt,
            "pathways_per_sweep": pathways, "frontier_items_per_s": parents / dt,
            "latency_ms_p50": float(np.percentile(lat, 50)), "latency_ms_p99": float(np.percentile(lat, 99)),
+           "latency_ms_max": float(lat.max()),
            "tile": {"waves_per_network": cfg[0], "networks_per_cu": cfg[1]},
            "networks_over_capacity": failed}
     if not args.no_cpu_baseline:

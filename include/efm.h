@@ -163,7 +163,9 @@ efm_status efm_result_destroy(efm_result *res);
  *   stream; the networks must outlive the call only.
  *   Errors: EFM_EINVAL (null, empty, too large, bad target), EFM_EDEVICE.
  * efm_batch_run: replays the graph on `stream` (NULL: the batch's stream) and
- *   blocks until it finishes; results and latencies then refer to this run.
+ *   blocks until it finishes; results and latencies then refer to this run.  The
+ *   first run takes the networks largest first; every later run takes them in
+ *   decreasing order of the previous run's latency.
  * efm_batch_result: network i's result (caller destroys it).  Its stats hold one
  *   summary entry (parents, children, emitted).  Errors: EFM_EINVAL before a run
  *   or for a bad index; EFM_ENOMEM / EFM_EOVERFLOW when that network overflowed a

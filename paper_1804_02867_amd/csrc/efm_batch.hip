@@ -766,6 +766,16 @@ efm_status efm_batch_run(efm_batch *b, void *stream) {
     BCHK(hipMemcpy(b->out_flux.data(), b->args.out_flux, b->out_flux.size() * 8, hipMemcpyDeviceToHost));
   }
   b->have_results = true;
+  // the next run pops the networks in decreasing order of this run's latency
+  // (longest processing time first), so the slowest ones start earliest
+  {
+    std::vector<int32_t> order(b->count);
+    for (int i = 0; i < b->count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+      return b->rec[x].t1 - b->rec[x].t0 > b->rec[y].t1 - b->rec[y].t0;
+    });
+    BCHK(hipMemcpy((void *)b->args.order, order.data(), sizeof(int32_t) * b->count, hipMemcpyHostToDevice));
+  }
   return EFM_OK;
 bad:
   return rc;
