@@ -1048,9 +1048,11 @@ efm_status efm_traces_append(efm_traces *T, const uint16_t *entries, const uint1
   int64_t pos = 0;
   for (int64_t i = 0; i < count; ++i) {
     if (lengths[i] > efm::kFeatMax) return fail(EFM_EINVAL, "record %lld longer than EFM_FEAT_MAX", (long long)i);
-    for (int e = 0; e < lengths[i]; ++e)
-      if ((int)(entries[i * efm::kFeatMax + e] >> 4) >= F)
-        return fail(EFM_EINVAL, "record %lld has an entry beyond the model input", (long long)i);
+    for (int e = 0; e < lengths[i]; ++e) {
+      const uint16_t v = entries[i * efm::kFeatMax + e];
+      if ((int)(v >> 4) >= F) return fail(EFM_EINVAL, "record %lld has an entry beyond the model input", (long long)i);
+      if ((v & 15u) > 7u) return fail(EFM_EINVAL, "record %lld has an entry code above 7", (long long)i);
+    }
     pos += labels[i] ? 1 : 0;
   }
   efm_status rc = EFM_OK;
