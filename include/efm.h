@@ -91,7 +91,8 @@ typedef struct {
   int64_t parents;      /* frontier members expanded at this level */
   int64_t children;     /* children generated (with repeats) */
   int64_t unique;       /* distinct children */
-  int64_t row_closed;   /* distinct children that needed the rank test */
+  int64_t row_closed;   /* distinct children that needed the rank test (depends on which parent
+                           inserted a child first, so it may vary between runs) */
   int64_t pruned;       /* of those, removed by the found-set prune */
   int64_t independent;  /* distinct children with independent columns */
   int64_t emitted;      /* elementary pathways found */

@@ -69,9 +69,11 @@ def test_struct_layouts_match_the_header(tmp_path):
 
 def test_header_constants_match_the_binding(tmp_path):
     src = tmp_path / "k.c"
-    src.write_text('#include <stdio.h>\n#include "efm.h"\nint main(void){printf("%d %d %u %d\\n", '
-                   'EFM_FEAT_MAX, EFM_TRACE_WORDS, EFM_OPT_LEARNED, EFM_MAX_DEPTH);return 0;}\n')
+    src.write_text('#include <stdio.h>\n#include "efm.h"\nint main(void){printf("%d %d %u %d %u %u %u %u %u\\n", '
+                   'EFM_FEAT_MAX, EFM_TRACE_WORDS, EFM_OPT_LEARNED, EFM_MAX_DEPTH, EFM_OPT_NO_PRUNE, '
+                   'EFM_OPT_EXACT_RANK, EFM_OPT_TIME_KERNELS, EFM_OPT_NO_GF2, EFM_OPT_AUTOTUNE);return 0;}\n')
     exe = tmp_path / "k"
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
-    assert got == [efm.FEAT_MAX, efm.TRACE_WORDS, efm.OPT_LEARNED, efm.MAX_DEPTH]
+    assert got == [efm.FEAT_MAX, efm.TRACE_WORDS, efm.OPT_LEARNED, efm.MAX_DEPTH, efm.OPT_NO_PRUNE,
+                   efm.OPT_EXACT_RANK, efm.OPT_TIME_KERNELS, efm.OPT_NO_GF2, efm.OPT_AUTOTUNE]
