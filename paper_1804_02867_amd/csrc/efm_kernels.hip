@@ -638,8 +638,25 @@ DEVI u64 key_word(const DevLevel &L, u64 ref, int w) {
 
 // Histogram of the undecided members' digits for pass `pass` (state and histogram
 // are double-buffered by pass parity).  Digits are highly skewed (the top bytes
-// of nearly all keys agree), so each wave groups its lanes by digit and adds one
-// count per distinct digit.
+// of nearly all keys agree), so each wave adds its lanes in groups of equal
+// digits (wave_hist_add).
+// Adds the wave's active digits to an LDS histogram: lanes that share a digit
+// with the first or second pending lane add as one group (the common case, since
+// most keys agree on most bytes); any other lane adds its own count.
+DEVI void wave_hist_add(uint32_t *h, bool act, uint32_t d) {
+  u64 pending = __ballot(act);
+  const int lane = lane_id();
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    if (!pending) return;
+    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)d, __ffsll((long long)pending) - 1);
+    const u64 m = __ballot(act && d == v) & pending;
+    if (lane == __ffsll((long long)m) - 1) atomicAdd(&h[v], (uint32_t)__popcll(m));
+    pending &= ~m;
+  }
+  if ((pending >> lane) & 1ull) atomicAdd(&h[d], 1u);
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void select_hist_kernel(DevLevel L, int byte, int refill, int pass) {
   __shared__ uint32_t h[256];
@@ -670,13 +687,7 @@ __global__ __launch_bounds__(256) void select_hist_kernel(DevLevel L, int byte, 
       }
       d = (uint32_t)((kw >> shift) & 0xFF);
     }
-    u64 pending = __ballot(act);
-    while (pending) {
-      const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)d, __ffsll((long long)pending) - 1);
-      const u64 m = __ballot(act && d == v) & pending;
-      if (lane == __ffsll((long long)m) - 1) atomicAdd(&h[v], (uint32_t)__popcll(m));
-      pending &= ~m;
-    }
+    wave_hist_add(h, act, d);
   }
   __syncthreads();
   if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
@@ -811,13 +822,7 @@ __global__ __launch_bounds__(256) void select_step_kernel(DevLevel L, int prev_b
         d = (uint32_t)((kw >> shift) & 0xFF);
       }
     }
-    u64 pending = __ballot(act);
-    while (pending) {
-      const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)d, __ffsll((long long)pending) - 1);
-      const u64 m = __ballot(act && d == v) & pending;
-      if (lane == __ffsll((long long)m) - 1) atomicAdd(&h[v], (uint32_t)__popcll(m));
-      pending &= ~m;
-    }
+    wave_hist_add(h, act, d);
   }
   __syncthreads();
   if (h[threadIdx.x]) atomicAdd(&hcur[threadIdx.x], h[threadIdx.x]);
