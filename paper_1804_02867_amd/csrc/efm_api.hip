@@ -294,8 +294,8 @@ Layout make_layout(const efm_network *N, const efm_enum_opts *o) {
   L.off_parq = take((size_t)L.fcap * 8);            // parents with row-closed children
   L.off_parmask = take((size_t)L.fcap * Wt * 8);
   L.off_exactq = take((size_t)L.ucap * 8);
-  L.off_sel = take((size_t)L.ucap);
-  L.off_skey = take((size_t)L.ucap * 8);
+  L.off_sel = take((size_t)efm::sel_stride(L.ucap));   // read four members at a time
+  L.off_skey = take((size_t)efm::sel_stride(L.ucap) * 8);
   L.off_fkeys = take((size_t)Wt * L.ecap * 8);
   L.off_fflux = take((size_t)L.ecap * efm::kMaxDepth * 8);
   L.off_xs = take((size_t)L.xwaves * std::max(N->mi, 1) * 64 * sizeof(efm::i128));
@@ -400,7 +400,7 @@ efm_status enumerate_impl(const efm_network *N, int32_t target, const efm_enum_o
   L.ucap = Lo.ucap;
   L.fcap = Lo.fcap;
   L.sel = (uint8_t *)(ws + Lo.off_sel);
-  L.skey = (u64 *)(ws + Lo.off_skey);
+  L.skey = (uint8_t *)(ws + Lo.off_skey);
   L.fkeys = (u64 *)(ws + Lo.off_fkeys);
   L.fflux = (int64_t *)(ws + Lo.off_fflux);
   L.ecap = Lo.ecap;

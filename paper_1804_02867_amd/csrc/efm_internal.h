@@ -117,7 +117,7 @@ struct DevLevel {
   const int32_t *Sx;      // [n]
   // truncation
   uint8_t *sel;           // [ucap] 0 rejected, 1 selected, 2 undecided
-  u64 *skey;              // [ucap] the key word the current selection byte lies in
+  uint8_t *skey;          // [8][sel_stride(ucap)] byte planes of the key word the current selection byte lies in
   uint32_t *hist;         // [3][256], by pass % 3
   SelState *selst;        // [2], by pass parity
   const uint32_t *sscore; // [ucap] learned ordering: score word ranked before the key, or null
@@ -128,6 +128,10 @@ struct DevLevel {
   int debug_prime;         // every rank test goes to exact arithmetic
   int no_gf2;              // skip the modulo-2 certificate
 };
+
+// Row stride of the selection's byte planes: the survivor capacity rounded up to
+// 256 bytes, so that every plane is aligned for 32-bit loads of four members.
+__host__ __device__ inline int64_t sel_stride(int64_t ucap) { return (ucap + 255) & ~(int64_t)255; }
 
 // kernel launchers (efm_kernels.hip)
 hipError_t launch_expand(const DevNet &net, const DevLevel &L, hipStream_t s);

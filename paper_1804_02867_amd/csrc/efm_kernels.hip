@@ -627,13 +627,52 @@ __global__ __launch_bounds__(64) void exact_kernel(DevNet net, DevLevel L) {
 
 // Radix selection of the frontier cap's smallest keys, one key byte per pass from
 // the most significant.  sel[i] is 2 while survivor i is undecided, then 1
-// (selected) or 0 (rejected).  skey[i] caches the key word the current byte
-// lies in; it is refilled when a pass enters a new word.
+// (selected) or 0 (rejected).  skey caches the key word the current byte lies in
+// as eight byte planes (plane b, member i at b * sel_stride + i), refilled when a
+// pass enters a new word, so that a pass reads only the bytes it compares.  Each
+// lane takes four consecutive members with 32-bit loads of sel and the planes.
 template <int W>
 DEVI u64 key_word(const DevLevel &L, u64 ref, int w) {
   const u64 p = ref >> 12;
   const int r = (int)((ref >> 1) & 0x7FF);
   return L.keys[(int64_t)w * L.fcap + p] | ((r >> 6) == w ? (1ull << (r & 63)) : 0ull);
+}
+
+DEVI uint32_t ld32(const uint8_t *p) { return *(const uint32_t *)p; }
+DEVI void st32(uint8_t *p, uint32_t v) { *(uint32_t *)p = v; }
+DEVI uint32_t byte_of(uint32_t v, int k) { return (v >> (8 * k)) & 0xFFu; }
+
+// Members i0..i0+3 flagged in act4 (bit k): load the key word of `byte` (or the
+// learned score word), store its eight byte planes and return the digits of `byte`.
+template <int W>
+DEVI void refill4(const DevLevel &L, int64_t i0, uint32_t act4, int byte, uint32_t (&d)[4]) {
+  const int64_t ps = sel_stride(L.ucap);
+  const int shift = (byte & 7) * 8;
+  uint32_t pw[8];
+#pragma unroll
+  for (int b = 0; b < 8; ++b) pw[b] = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    if ((act4 >> k) & 1u) {
+      const int64_t i = i0 + k;
+      const u64 kw = (byte >> 3) >= W ? (u64)L.sscore[i] : key_word<W>(L, L.surv[i], byte >> 3);
+#pragma unroll
+      for (int b = 0; b < 8; ++b) pw[b] |= (uint32_t)((kw >> (8 * b)) & 0xFF) << (8 * k);
+      d[k] = (uint32_t)((kw >> shift) & 0xFF);
+    }
+  }
+  if (act4) {
+#pragma unroll
+    for (int b = 0; b < 8; ++b) st32(L.skey + b * ps + i0, pw[b]);
+  }
+}
+
+// bit k set when member i0+k exists and is undecided
+DEVI uint32_t undecided4(uint32_t s4, int64_t i0, int64_t n) {
+  uint32_t a = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) a |= (i0 + k < n && byte_of(s4, k) == 2u) ? (1u << k) : 0u;
+  return a;
 }
 
 // Histogram of the undecided members' digits for pass `pass` (state and histogram
@@ -666,29 +705,27 @@ __global__ __launch_bounds__(256) void select_hist_kernel(DevLevel L, int byte, 
   const int64_t n = min((int64_t)L.counters[cslot(kSurv)], L.ucap);
   h[threadIdx.x] = 0;
   __syncthreads();
+  const int64_t ps = sel_stride(L.ucap);
   const int lane = lane_id();
-  const int shift = (byte & 7) * 8;
+  const int64_t ng = (n + 3) >> 2;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
-    const int64_t i = base + lane;
-    const bool act = i < n && L.sel[i] == 2;
-    if (__ballot(act) == 0) continue;
-    uint32_t d = 0;
-    if (act) {
-      u64 kw;
-      if (refill) {
-        // word W is the learned score word (ascending = higher score), ranked
-        // before every word of the key
-        kw = (byte >> 3) >= W ? (u64)L.sscore[i] : key_word<W>(L, L.surv[i], byte >> 3);
-        L.skey[i] = kw;
-      } else {
-        kw = L.skey[i];
-      }
-      d = (uint32_t)((kw >> shift) & 0xFF);
+  for (int64_t base = wave * 64; base < ng; base += nwaves * 64) {
+    const int64_t g = base + lane;
+    const int64_t i0 = g * 4;
+    uint32_t s4 = 0, c4 = 0;
+    if (g < ng) {
+      s4 = ld32(L.sel + i0);
+      if (!refill) c4 = ld32(L.skey + (byte & 7) * ps + i0);
     }
-    wave_hist_add(h, act, d);
+    const uint32_t act4 = g < ng ? undecided4(s4, i0, n) : 0u;
+    if (__ballot(act4 != 0) == 0) continue;
+    uint32_t d[4] = {byte_of(c4, 0), byte_of(c4, 1), byte_of(c4, 2), byte_of(c4, 3)};
+    if (refill) refill4<W>(L, i0, act4, byte, d);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wave_hist_add(h, (act4 >> k) & 1u, d[k]);
   }
+  (void)lane;
   __syncthreads();
   if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
 }
@@ -737,15 +774,26 @@ __global__ __launch_bounds__(256) void select_split_kernel(DevLevel L, int byte,
   __syncthreads();
   if (dec[2]) return;                       // one digit only: nothing decided here
   const uint32_t digit = dec[0];
-  const int all_sel = (int)dec[1];
-  const int shift = (byte & 7) * 8;
+  const bool all_sel = dec[1] != 0;
+  const int64_t ps = sel_stride(L.ucap);
   const int64_t n = min((int64_t)L.counters[cslot(kSurv)], L.ucap);
+  const int64_t ng = (n + 3) >> 2;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    if (L.sel[i] != 2) continue;
-    const uint32_t d = (uint32_t)((L.skey[i] >> shift) & 0xFF);
-    if (d < digit || (d == digit && all_sel)) L.sel[i] = 1;
-    else if (d > digit) L.sel[i] = 0;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < ng; g += stride) {
+    const int64_t i0 = g * 4;
+    const uint32_t s4 = ld32(L.sel + i0);
+    const uint32_t c4 = ld32(L.skey + (byte & 7) * ps + i0);
+    const uint32_t act4 = undecided4(s4, i0, n);
+    if (!act4) continue;
+    uint32_t o4 = s4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (!((act4 >> k) & 1u)) continue;
+      const uint32_t d = byte_of(c4, k);
+      const uint32_t v = (d < digit || (d == digit && all_sel)) ? 1u : (d > digit ? 0u : 2u);
+      o4 = (o4 & ~(0xFFu << (8 * k))) | (v << (8 * k));
+    }
+    if (o4 != s4) st32(L.sel + i0, o4);
   }
 }
 
@@ -798,32 +846,45 @@ __global__ __launch_bounds__(256) void select_step_kernel(DevLevel L, int prev_b
   const bool decides = !dec[2];
   const uint32_t digit = dec[0];
   const bool all_sel = dec[1] != 0;
-  const int pshift = (prev_byte & 7) * 8, shift = (byte & 7) * 8;
+  const int64_t ps = sel_stride(L.ucap);
   const int lane = lane_id();
   const int64_t n = min((int64_t)L.counters[cslot(kSurv)], L.ucap);
+  const int64_t ng = (n + 3) >> 2;
   const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t base = wave * 64; base < n; base += nwaves * 64) {
-    const int64_t i = base + lane;
-    bool act = i < n && L.sel[i] == 2;
-    uint32_t d = 0;
-    if (act) {
-      u64 kw = L.skey[i];
-      if (decides) {
-        const uint32_t dp = (uint32_t)((kw >> pshift) & 0xFF);
-        if (dp < digit || (dp == digit && all_sel)) { L.sel[i] = 1; act = false; }
-        else if (dp > digit) { L.sel[i] = 0; act = false; }
-      }
-      if (act) {
-        if (refill) {
-          kw = (byte >> 3) >= W ? (u64)L.sscore[i] : key_word<W>(L, L.surv[i], byte >> 3);
-          L.skey[i] = kw;
-        }
-        d = (uint32_t)((kw >> shift) & 0xFF);
-      }
+  for (int64_t base = wave * 64; base < ng; base += nwaves * 64) {
+    const int64_t g = base + lane;
+    const int64_t i0 = g * 4;
+    uint32_t s4 = 0, p4 = 0, c4 = 0;
+    if (g < ng) {
+      s4 = ld32(L.sel + i0);
+      if (decides) p4 = ld32(L.skey + (prev_byte & 7) * ps + i0);
+      if (!refill) c4 = ld32(L.skey + (byte & 7) * ps + i0);
     }
-    wave_hist_add(h, act, d);
+    uint32_t act4 = g < ng ? undecided4(s4, i0, n) : 0u;
+    if (__ballot(act4 != 0) == 0) continue;
+    if (decides && act4) {
+      uint32_t o4 = s4;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (!((act4 >> k) & 1u)) continue;
+        const uint32_t dp = byte_of(p4, k);
+        if (dp < digit || (dp == digit && all_sel)) {
+          o4 = (o4 & ~(0xFFu << (8 * k))) | (1u << (8 * k));
+          act4 &= ~(1u << k);
+        } else if (dp > digit) {
+          o4 &= ~(0xFFu << (8 * k));
+          act4 &= ~(1u << k);
+        }
+      }
+      if (o4 != s4) st32(L.sel + i0, o4);
+    }
+    uint32_t d[4] = {byte_of(c4, 0), byte_of(c4, 1), byte_of(c4, 2), byte_of(c4, 3)};
+    if (refill) refill4<W>(L, i0, act4, byte, d);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) wave_hist_add(h, (act4 >> k) & 1u, d[k]);
   }
+  (void)lane;
   __syncthreads();
   if (h[threadIdx.x]) atomicAdd(&hcur[threadIdx.x], h[threadIdx.x]);
 }
