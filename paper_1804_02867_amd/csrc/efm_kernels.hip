@@ -696,6 +696,29 @@ DEVI void wave_hist_add(uint32_t *h, bool act, uint32_t d) {
   if ((pending >> lane) & 1ull) atomicAdd(&h[d], 1u);
 }
 
+// Boundary digit of a finished 256-bin histogram: the first v (at most 255)
+// whose inclusive prefix sum reaches `needed`, the count below it and its own
+// count.  Every thread of the 256-thread block calls it (block-wide scan in LDS).
+DEVI void hist_boundary(const uint32_t *hist, int64_t needed, int &v, int64_t &cum, int64_t &hv) {
+  __shared__ int64_t sc[256];
+  __shared__ int vsel;
+  const int t = threadIdx.x;
+  sc[t] = (int64_t)hist[t];
+  if (t == 0) vsel = 255;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const int64_t add = t >= off ? sc[t - off] : 0;
+    __syncthreads();
+    sc[t] += add;
+    __syncthreads();
+  }
+  if (t < 255 && sc[t] >= needed) atomicMin(&vsel, t);
+  __syncthreads();
+  v = vsel;
+  hv = (int64_t)hist[v];
+  cum = sc[v] - hv;
+}
+
 template <int W>
 __global__ __launch_bounds__(256) void select_hist_kernel(DevLevel L, int byte, int refill, int pass) {
   __shared__ uint32_t h[256];
@@ -747,14 +770,10 @@ __global__ __launch_bounds__(256) void select_split_kernel(DevLevel L, int byte,
     if (lead && threadIdx.x == 0) *nx = *st;
     return;
   }
+  int v;
+  int64_t cum, hv;
+  hist_boundary(hist, st->needed, v, cum, hv);
   if (threadIdx.x == 0) {
-    int64_t cum = 0;
-    int v = 0;
-    for (v = 0; v < 255; ++v) {
-      if (cum + (int64_t)hist[v] >= st->needed) break;
-      cum += hist[v];
-    }
-    const int64_t hv = hist[v];
     const int64_t remaining = st->needed - cum;
     const uint32_t all_sel = hv == remaining ? 1u : 0u;
     dec[0] = (uint32_t)v;
@@ -818,14 +837,10 @@ __global__ __launch_bounds__(256) void select_step_kernel(DevLevel L, int prev_b
     return;
   }
   h[threadIdx.x] = 0;
+  int v;
+  int64_t cum, hv;
+  hist_boundary(hprev, st->needed, v, cum, hv);
   if (threadIdx.x == 0) {
-    int64_t cum = 0;
-    int v = 0;
-    for (v = 0; v < 255; ++v) {
-      if (cum + (int64_t)hprev[v] >= st->needed) break;
-      cum += hprev[v];
-    }
-    const int64_t hv = hprev[v];
     const int64_t remaining = st->needed - cum;
     const uint32_t all_sel = hv == remaining ? 1u : 0u;
     dec[0] = (uint32_t)v;
