@@ -280,7 +280,7 @@ Layout make_layout(const efm_network *N, const efm_enum_opts *o) {
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o2 = off; off += align256(bytes); return o2; };
   L.off_counters = take(efm::kNumCounters * efm::kCounterStride * 8);
-  L.off_hist = take(3 * 256 * 4);
+  L.off_hist = take(3 * efm::kHistCopies * 256 * 4);
   L.off_selst = take(2 * sizeof(efm::SelState));
   L.off_root = take((size_t)Wt * 8);
   L.off_sx = take((size_t)N->n * 4);
@@ -497,7 +497,7 @@ efm_status enumerate_impl(const efm_network *N, int32_t target, const efm_enum_o
       use_sel = 1;
       status |= EFM_FRONTIER_TRUNCATED;
       HIPCHK(hipMemsetAsync(L.sel, 2, (size_t)nsurv, s));
-      HIPCHK(hipMemsetAsync(L.hist, 0, 3 * 256 * 4, s));
+      HIPCHK(hipMemsetAsync(L.hist, 0, 3 * efm::kHistCopies * 256 * 4, s));
       sel_init = efm::SelState{};
       sel_init.needed = o.frontier_cap;
       sel_init.nb = nsurv;

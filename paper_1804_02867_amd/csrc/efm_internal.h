@@ -44,6 +44,10 @@ enum Counter {
 // a cache line.
 constexpr int kCounterStride = 32;
 __host__ __device__ inline size_t cslot(int c) { return (size_t)c * kCounterStride; }
+// Copies of each selection histogram in device memory: the blocks of a pass add
+// into different copies, so that skewed digits (one bin for nearly every key) do
+// not put every block's atomic on one address; readers sum the copies.
+constexpr int kHistCopies = 16;
 constexpr int kMaxEnt = 16;        // column entries kept in registers by the rank test
 
 enum FlagBits : u64 {
@@ -118,7 +122,7 @@ struct DevLevel {
   // truncation
   uint8_t *sel;           // [ucap] 0 rejected, 1 selected, 2 undecided
   uint8_t *skey;          // [8][sel_stride(ucap)] byte planes of the key word the current selection byte lies in
-  uint32_t *hist;         // [3][256], by pass % 3
+  uint32_t *hist;         // [3][kHistCopies][256], by pass % 3; block b adds to copy b % kHistCopies
   SelState *selst;        // [2], by pass parity
   const uint32_t *sscore; // [ucap] learned ordering: score word ranked before the key, or null
   u64 *counters;

@@ -701,9 +701,14 @@ DEVI void wave_hist_add(uint32_t *h, bool act, uint32_t d) {
 // count.  Every thread of the 256-thread block calls it (block-wide scan in LDS).
 DEVI void hist_boundary(const uint32_t *hist, int64_t needed, int &v, int64_t &cum, int64_t &hv) {
   __shared__ int64_t sc[256];
+  __shared__ int64_t bin[256];
   __shared__ int vsel;
   const int t = threadIdx.x;
-  sc[t] = (int64_t)hist[t];
+  int64_t c = 0;
+#pragma unroll
+  for (int k = 0; k < kHistCopies; ++k) c += hist[k * 256 + t];
+  sc[t] = c;
+  bin[t] = c;
   if (t == 0) vsel = 255;
   __syncthreads();
   for (int off = 1; off < 256; off <<= 1) {
@@ -715,7 +720,7 @@ DEVI void hist_boundary(const uint32_t *hist, int64_t needed, int &v, int64_t &c
   if (t < 255 && sc[t] >= needed) atomicMin(&vsel, t);
   __syncthreads();
   v = vsel;
-  hv = (int64_t)hist[v];
+  hv = bin[v];
   cum = sc[v] - hv;
 }
 
@@ -724,7 +729,7 @@ __global__ __launch_bounds__(256) void select_hist_kernel(DevLevel L, int byte, 
   __shared__ uint32_t h[256];
   const SelState *st = L.selst + (pass & 1);
   if (st->done) return;
-  uint32_t *hist = L.hist + 256 * (pass % 3);
+  uint32_t *hist = L.hist + kHistCopies * 256 * (pass % 3);
   const int64_t n = min((int64_t)L.counters[cslot(kSurv)], L.ucap);
   h[threadIdx.x] = 0;
   __syncthreads();
@@ -750,7 +755,7 @@ __global__ __launch_bounds__(256) void select_hist_kernel(DevLevel L, int byte, 
   }
   (void)lane;
   __syncthreads();
-  if (h[threadIdx.x]) atomicAdd(&hist[threadIdx.x], h[threadIdx.x]);
+  if (h[threadIdx.x]) atomicAdd(&hist[(blockIdx.x % kHistCopies) * 256 + threadIdx.x], h[threadIdx.x]);
 }
 
 // Every block derives the pass's decision from the finished histogram: the
@@ -763,9 +768,10 @@ __global__ __launch_bounds__(256) void select_split_kernel(DevLevel L, int byte,
   __shared__ int64_t rem;
   const SelState *st = L.selst + (pass & 1);
   SelState *nx = L.selst + ((pass + 1) & 1);
-  const uint32_t *hist = L.hist + 256 * (pass % 3);
+  const uint32_t *hist = L.hist + kHistCopies * 256 * (pass % 3);
   const bool lead = blockIdx.x == 0;
-  if (lead) L.hist[256 * ((pass + 1) % 3) + threadIdx.x] = 0;
+  if (lead)
+    for (int k = 0; k < kHistCopies; ++k) L.hist[kHistCopies * 256 * ((pass + 1) % 3) + k * 256 + threadIdx.x] = 0;
   if (st->done) {
     if (lead && threadIdx.x == 0) *nx = *st;
     return;
@@ -828,10 +834,11 @@ __global__ __launch_bounds__(256) void select_step_kernel(DevLevel L, int prev_b
   __shared__ uint32_t h[256];
   const SelState *st = L.selst + ((pass - 1) & 1);
   SelState *nx = L.selst + (pass & 1);
-  const uint32_t *hprev = L.hist + 256 * ((pass - 1) % 3);
-  uint32_t *hcur = L.hist + 256 * (pass % 3);
+  const uint32_t *hprev = L.hist + kHistCopies * 256 * ((pass - 1) % 3);
+  uint32_t *hcur = L.hist + kHistCopies * 256 * (pass % 3);
   const bool lead = blockIdx.x == 0;
-  if (lead) L.hist[256 * ((pass + 1) % 3) + threadIdx.x] = 0;
+  if (lead)
+    for (int k = 0; k < kHistCopies; ++k) L.hist[kHistCopies * 256 * ((pass + 1) % 3) + k * 256 + threadIdx.x] = 0;
   if (st->done) {
     if (lead && threadIdx.x == 0) *nx = *st;
     return;
@@ -901,7 +908,7 @@ __global__ __launch_bounds__(256) void select_step_kernel(DevLevel L, int prev_b
   }
   (void)lane;
   __syncthreads();
-  if (h[threadIdx.x]) atomicAdd(&hcur[threadIdx.x], h[threadIdx.x]);
+  if (h[threadIdx.x]) atomicAdd(&hcur[(blockIdx.x % kHistCopies) * 256 + threadIdx.x], h[threadIdx.x]);
 }
 
 // Writes the next frontier.  Without a cap the survivor order is kept (position =
