@@ -41,6 +41,7 @@ constexpr int kWaveBuf = 128;
 struct WaveBuf {
   u64 *lds;
   int n;
+  int cap = kWaveBuf;     // entries the LDS buffer holds
 };
 
 DEVI void wbuf_flush(WaveBuf &b, u64 *list, u64 *counter, int64_t cap, u64 *flags) {
@@ -63,9 +64,35 @@ DEVI void wbuf_push(WaveBuf &b, bool pred, u64 val, u64 *list, u64 *counter, int
   const u64 mask = __ballot(pred);
   const int cnt = __popcll(mask);
   if (cnt == 0) return;
-  if (b.n + cnt > kWaveBuf) wbuf_flush(b, list, counter, cap, flags);
+  if (b.n + cnt > b.cap) wbuf_flush(b, list, counter, cap, flags);
   if (pred) b.lds[b.n + __popcll(mask & lanes_below(lane_id()))] = val;
   b.n += cnt;
+}
+
+// Final flush of every wave's buffer in the block with one global atomic for the
+// block (a list counter is shared by every block, so its atomics serialize).
+// Every thread of the block (at most 4 waves) must call it.
+DEVI void wbuf_flush_block(WaveBuf &b, u64 *list, u64 *counter, int64_t cap, u64 *flags) {
+  __shared__ u64 wcnt[4], wbase[4];
+  const int wib = threadIdx.x >> 6, lane = lane_id();
+  __threadfence_block();
+  if (lane == 0) wcnt[wib] = (u64)b.n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (int)(blockDim.x >> 6);
+    u64 tot = 0;
+    for (int w = 0; w < nw; ++w) tot += wcnt[w];
+    u64 base = tot ? atomicAdd(counter, tot) : 0ull;
+    for (int w = 0; w < nw; ++w) { wbase[w] = base; base += wcnt[w]; }
+  }
+  __syncthreads();
+  const u64 base = wbase[wib];
+  for (int i = lane; i < b.n; i += 64) {
+    const u64 idx = base + (u64)i;
+    if ((int64_t)idx < cap) list[idx] = b.lds[i];
+    else atomicOr(flags, (u64)kFlagQueueOverflow);
+  }
+  b.n = 0;
 }
 
 // Block-wide sum of per-thread counts into global counters (end of kernel; every

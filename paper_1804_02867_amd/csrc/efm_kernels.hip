@@ -146,9 +146,10 @@ __global__ __launch_bounds__(256) void expand_kernel(DevNet net, DevLevel L) {
   }
 
   // children: uniform trip count per wave so the ballots stay converged
-  __shared__ u64 stage[4][kWaveBuf];
+  constexpr int kExpandBuf = 512;      // most waves flush once, at the end
+  __shared__ u64 stage[4][kExpandBuf];
   const int wib = threadIdx.x >> 6;
-  WaveBuf bsurv{stage[wib], 0};
+  WaveBuf bsurv{stage[wib], 0, kExpandBuf};
   u64 n_unique = 0, n_indep = 0, n_capped = 0, n_rc = 0;
   u64 rcm[W];                  // this parent's distinct row-closed children
 #pragma unroll
@@ -187,7 +188,7 @@ __global__ __launch_bounds__(256) void expand_kernel(DevNet net, DevLevel L) {
     n_indep += (uniq && !rc) ? 1 : 0;
     n_capped += (uniq && !rc && !keep_indep) ? 1 : 0;
   }
-  wbuf_flush(bsurv, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
+  wbuf_flush_block(bsurv, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
   {
     // one rank-queue entry per parent that has row-closed children
     bool any = false;
@@ -500,8 +501,8 @@ __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L
       if (i1 < nitems) rank_parent_one<W, MW>(net, L, i1, prune, nf, keep_indep, colx[wib], bsurv, bslow, cnt);
     }
   }
-  wbuf_flush(bsurv, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
-  wbuf_flush(bslow, L.rankq, &L.counters[cslot(kRankQ)], L.ucap, &L.counters[cslot(kFlags)]);
+  wbuf_flush_block(bsurv, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
+  wbuf_flush_block(bslow, L.rankq, &L.counters[cslot(kRankQ)], L.ucap, &L.counters[cslot(kFlags)]);
   u64 v[4] = {cnt.indep, cnt.pruned, cnt.capped, cnt.rows};
   const int slots[4] = {kIndep, kPruned, kCapped, kRankRows};
   block_counts<4>(v, L.counters, slots);
@@ -560,8 +561,8 @@ __global__ __launch_bounds__(256) void rank_kernel(DevNet net, DevLevel L, int p
     wbuf_push(bexact, !indep && lane == 0, ref, L.exactq, &L.counters[cslot(kExactQ)], L.ucap,
               &L.counters[cslot(kFlags)]);
   }
-  wbuf_flush(bsurv, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
-  wbuf_flush(bexact, L.exactq, &L.counters[cslot(kExactQ)], L.ucap, &L.counters[cslot(kFlags)]);
+  wbuf_flush_block(bsurv, L.surv, &L.counters[cslot(kSurv)], L.ucap, &L.counters[cslot(kFlags)]);
+  wbuf_flush_block(bexact, L.exactq, &L.counters[cslot(kExactQ)], L.ucap, &L.counters[cslot(kFlags)]);
   u64 v[3] = {n_indep, n_pruned, n_capped};
   const int slots[3] = {kIndep, kPruned, kCapped};
   block_counts<3>(v, L.counters, slots);
