@@ -95,6 +95,26 @@ DEVI void wbuf_flush_block(WaveBuf &b, u64 *list, u64 *counter, int64_t cap, u64
   b.n = 0;
 }
 
+// Slot of this lane in a list that every lane with pred appends one entry to, with
+// one global atomic for the block.  Every thread of the block (at most 4 waves)
+// must call it; the result is meaningful where pred is set.
+DEVI u64 block_append_index(bool pred, u64 *counter) {
+  __shared__ u64 acnt[4], abase[4];
+  const int wib = threadIdx.x >> 6, lane = lane_id();
+  const u64 m = __ballot(pred);
+  if (lane == 0) acnt[wib] = (u64)__popcll(m);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (int)(blockDim.x >> 6);
+    u64 tot = 0;
+    for (int w = 0; w < nw; ++w) tot += acnt[w];
+    u64 base = tot ? atomicAdd(counter, tot) : 0ull;
+    for (int w = 0; w < nw; ++w) { abase[w] = base; base += acnt[w]; }
+  }
+  __syncthreads();
+  return abase[wib] + (u64)__popcll(m & lanes_below(lane));
+}
+
 // Block-wide sum of per-thread counts into global counters (end of kernel; every
 // thread of the block must call it).
 template <int NC>

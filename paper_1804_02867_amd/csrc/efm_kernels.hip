@@ -194,21 +194,14 @@ __global__ __launch_bounds__(256) void expand_kernel(DevNet net, DevLevel L) {
     bool any = false;
 #pragma unroll
     for (int w = 0; w < W; ++w) any = any || rcm[w] != 0;
-    const u64 m = __ballot(any);
-    if (m) {
-      const int leader = __ffsll((long long)m) - 1;
-      u64 b0 = 0;
-      if (lane_id() == leader) b0 = atomicAdd(&L.counters[cslot(kParQ)], (u64)__popcll(m));
-      b0 = __shfl(b0, leader);
-      if (any) {
-        const u64 idx = b0 + (u64)__popcll(m & lanes_below(lane_id()));
-        if ((int64_t)idx < L.fcap) {           // one entry per parent: at most the frontier capacity
-          L.parq[idx] = (u64)p;
+    const u64 idx = block_append_index(any, &L.counters[cslot(kParQ)]);
+    if (any) {
+      if ((int64_t)idx < L.fcap) {             // one entry per parent: at most the frontier capacity
+        L.parq[idx] = (u64)p;
 #pragma unroll
-          for (int w = 0; w < W; ++w) L.parmask[(int64_t)idx * W + w] = rcm[w];
-        } else {
-          atomicOr(&L.counters[cslot(kFlags)], (u64)kFlagQueueOverflow);
-        }
+        for (int w = 0; w < W; ++w) L.parmask[(int64_t)idx * W + w] = rcm[w];
+      } else {
+        atomicOr(&L.counters[cslot(kFlags)], (u64)kFlagQueueOverflow);
       }
     }
   }
@@ -469,7 +462,8 @@ DEVI void rank_parent_two(const DevNet &net, const DevLevel &L, int64_t i0, int6
 
 template <int W, int MW>
 __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L, int prune) {
-  __shared__ u64 stage[2][4][kWaveBuf];
+  constexpr int kRankBuf = 256;
+  __shared__ u64 stage[2][4][kRankBuf];
   __shared__ uint16_t colx[4][64];
   const int wib = threadIdx.x >> 6;
   const int wpb = blockDim.x >> 6;
@@ -477,7 +471,7 @@ __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L
   const bool keep_indep = L.level + 1 < L.depth_cap;
   const int64_t nf = min((int64_t)L.nfound_prev, L.ecap);
   const bool pairs_ok = !(prune && nf > 0) && !L.debug_prime && !L.no_gf2;
-  WaveBuf bsurv{stage[0][wib], 0}, bslow{stage[1][wib], 0};
+  WaveBuf bsurv{stage[0][wib], 0, kRankBuf}, bslow{stage[1][wib], 0, kRankBuf};
   RankCounts cnt;
 
   // items in pairs: two narrow parents share the wave, otherwise one at a time
@@ -516,14 +510,15 @@ __global__ __launch_bounds__(256) void rank_parent_kernel(DevNet net, DevLevel L
 // there are unpeeled columns.
 template <int W, int MW>
 __global__ __launch_bounds__(256) void rank_kernel(DevNet net, DevLevel L, int prune, int kq_max) {
-  __shared__ u64 stage[2][4][kWaveBuf];
+  constexpr int kRankBuf = 256;
+  __shared__ u64 stage[2][4][kRankBuf];
   const int wib = threadIdx.x >> 6;
   const int lane = lane_id();
   const int wpb = blockDim.x >> 6;
   const int64_t nitems = min((int64_t)L.counters[cslot(kRankQ)], L.ucap);
   const bool keep_indep = L.level + 1 < L.depth_cap;
   const int64_t nf = min((int64_t)L.nfound_prev, L.ecap);
-  WaveBuf bsurv{stage[0][wib], 0}, bexact{stage[1][wib], 0};
+  WaveBuf bsurv{stage[0][wib], 0, kRankBuf}, bexact{stage[1][wib], 0, kRankBuf};
   u64 n_indep = 0, n_pruned = 0, n_capped = 0;
 
   for (int64_t item = (int64_t)blockIdx.x * wpb + wib; item < nitems; item += (int64_t)gridDim.x * wpb) {
