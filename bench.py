@@ -32,7 +32,7 @@ MULMOD_PEAK_T = 256 * 128 * 2.4e9 / 12 / 1e12
 # HBM bytes per launch from the rocprofv3 FETCH_SIZE / WRITE_SIZE runs of one bench
 # step (calibrated on a 1 GiB device copy: FETCH_SIZE x 2, WRITE_SIZE x 1); None
 # when the kernel changed after the counters were taken.
-TRAFFIC_PER_LAUNCH = {"expand": 754.1e6, "rank": 135.8e6}
+TRAFFIC_PER_LAUNCH = {"expand": 749.8e6, "rank": 135.9e6}
 
 
 def expand_bytes(level: dict, W: int) -> float:
