@@ -35,8 +35,9 @@ DEVI void wave_count(bool pred, u64 *counter) {
   if (mask != 0 && lane_id() == __ffsll((long long)mask) - 1) atomicAdd(counter, (u64)__popcll(mask));
 }
 
-// Wave-private staging of list appends in LDS (128 entries): one global atomic per
-// flush instead of one per wave and step.  `n` is wave-uniform.
+// Wave-private staging of list appends in LDS (`cap` entries, kWaveBuf unless the
+// kernel gives more): one global atomic per flush instead of one per wave and
+// step.  `n` is wave-uniform.
 constexpr int kWaveBuf = 128;
 struct WaveBuf {
   u64 *lds;
